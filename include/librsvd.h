@@ -1,0 +1,166 @@
+/*
+ * librsvd -- randomized truncated SVD on one AMD MI355X (gfx950).
+ *
+ * The method is the randomized SVD of Kohn et al., "Probabilistic low-rank
+ * factorization accelerates tensor network simulations of critical quantum
+ * many-body ground states", Sec. II.B, Alg. RSVD: a Gaussian test matrix
+ * Omega (n x l), the sample Y = (A A^T)^q A Omega formed as a power iteration
+ * with an orthonormalisation after every product, Q = orthonormal basis of Y,
+ * the SVD of B = Q^T A, left vectors Q Utilde, right vectors Vtilde.  The
+ * deterministic comparison is Alg. TSVD of Sec. II.A (full SVD, then keep the
+ * leading triplets).
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are row-major with an explicit leading dimension in elements.
+ *  - All matrix, vector and scalar-output pointers are DEVICE pointers owned
+ *    by the caller; the library never frees them.  Library-owned device
+ *    memory lives only inside an rsvd_plan_t (workspace, descriptors, graph)
+ *    or in the small plan cache of the one-shot calls.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *  - k is clamped to min(m, n) (small symmetry sectors routinely ask for more
+ *    triplets than the block has).  l = min(k + p, m, n).
+ *  - Outputs: U is m x k (ldu >= k), S has k entries, VT is k x n (ldvt >= n).
+ *    S is sorted in descending order.  Only the first k_kept triplets are
+ *    filled; columns k_kept..k-1 of U, rows k_kept..k-1 of VT and entries
+ *    k_kept..k-1 of S are zero.
+ *  - Sign convention: the entry of largest magnitude of every kept column of
+ *    U is positive (lowest row index on ties); VT follows.
+ *  - Truncation (paper Sec. II.A measures the truncation error in the
+ *    Frobenius norm): w(k') = discarded squared Frobenius weight when k'
+ *    triplets are kept.  k_kept = k when delta_trunc == 0, otherwise the
+ *    smallest k' >= 1 with w(k') <= delta_trunc * ||A||_F^2, capped at k.
+ *    ||A||_F = 0 gives k_kept = 0 and w = 0.  The reported discarded weight
+ *    is the absolute w(k_kept), in FP64.  For the RSVD it is
+ *    ||A||_F^2 - sum_{j<=k_kept} sigma_j^2, which equals ||A - U S VT||_F^2;
+ *    for the full SVD it is the tail sum of the discarded sigma_j^2.
+ *  - Gaussian test matrix: entry (i, j) of Omega for seed s is the
+ *    Box-Muller normal built from Philox4x32-10 with key (s mod 2^32, s >> 32)
+ *    and counter (i/2, j, 0, 0): u1 = 1 - ((w0:w1) >> 11) 2^-53,
+ *    u2 = ((w2:w3) >> 11) 2^-53, r = sqrt(-2 ln u1), r cos(2 pi u2) for even
+ *    i and r sin(2 pi u2) for odd i.  A problem's Omega depends only on its
+ *    seed, never on its position in a batch.
+ *
+ * Errors: every entry point returns an rsvd_status_t and never throws.
+ * RSVD_ERR_INVALID leaves all outputs untouched.  rsvd_last_error() returns a
+ * thread-local description of the last failure.
+ */
+#ifndef LIBRSVD_H
+#define LIBRSVD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RSVD_OK = 0,
+    RSVD_ERR_INVALID = -1,   /* bad argument: sizes, leading dimensions, null pointers, delta < 0 or NaN */
+    RSVD_ERR_ALLOC = -2,     /* device or pinned-host allocation failed */
+    RSVD_ERR_HIP = -3,       /* a HIP runtime call failed */
+    RSVD_ERR_NONFINITE = -4, /* ||A||_F^2 is not finite (NaN or Inf in A); outputs zero, k_kept = 0 */
+    RSVD_ERR_NOCONV = -5     /* Jacobi sweep cap reached; outputs are still filled */
+} rsvd_status_t;
+
+/* Storage type of A, U, S and VT. */
+typedef enum { RSVD_F64 = 0, RSVD_F32 = 1 } rsvd_dtype_t;
+
+/* Arithmetic of the sketch and power-iteration products (Y = A Omega, A^T Q,
+ * A Z).  The Gram matrices, Cholesky factors, the projection B = Q^T A (from
+ * the stored A, upcast exactly), the small Jacobi SVD and the back-projection
+ * always run in FP64.  BF16 rounds A, Omega and Q to bf16 and accumulates in
+ * FP32; F32 rounds them to FP32 and accumulates in FP32. */
+typedef enum { RSVD_PREC_F64 = 0, RSVD_PREC_F32 = 1, RSVD_PREC_BF16 = 2 } rsvd_prec_t;
+
+/*
+ * rsvd_truncate -- one randomized truncated SVD (Alg. RSVD, Sec. II.B).
+ *   A        device, m x n, leading dimension lda >= n, dtype dt
+ *   k, p, q  target rank (>= 1), oversampling (>= 0), power iterations (>= 0)
+ *   seed     Gaussian test-matrix seed (see conventions)
+ *   delta_trunc  relative discarded-weight threshold (>= 0; 0 disables)
+ *   prec     arithmetic of the sketch / power products
+ *   U, S, VT device outputs (dtype dt), see conventions
+ *   discarded_weight  device double[1]; k_kept  device int64_t[1]
+ * Blocking: returns after the factorisation has completed on the stream, so
+ * that RSVD_ERR_NONFINITE / RSVD_ERR_NOCONV can be reported.  Plans are cached
+ * per shape, so repeated calls of one shape reuse their workspace and graph.
+ */
+int rsvd_truncate(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t lda, int64_t k,
+                  int64_t p, int64_t q, uint64_t seed, double delta_trunc, rsvd_prec_t prec, void* U,
+                  int64_t ldu, void* S, void* VT, int64_t ldvt, double* discarded_weight,
+                  int64_t* k_kept, void* stream);
+
+/*
+ * fullsvd_truncate -- deterministic truncation by the full SVD (Alg. TSVD,
+ * Sec. II.A), computed by block one-sided Jacobi in FP64 on A (m <= n) or A^T
+ * (m > n).  Arguments as for rsvd_truncate.  Blocking, cached like it.
+ */
+int fullsvd_truncate(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t lda, int64_t k,
+                     double delta_trunc, void* U, int64_t ldu, void* S, void* VT, int64_t ldvt,
+                     double* discarded_weight, int64_t* k_kept, void* stream);
+
+/*
+ * rsvd_gaussian -- the Gaussian test matrix Omega (n x l, row-major, FP64,
+ * device output) that rsvd_truncate draws for this seed (Alg. RSVD step 1,
+ * layout in the conventions above).  Blocking.  Lets callers reproduce or
+ * differentiate with the exact test matrix of a factorisation.
+ */
+int rsvd_gaussian(uint64_t seed, int64_t n, int64_t l, double* omega, void* stream);
+
+/*
+ * rsvd_philox4x32_10 -- raw Philox4x32-10 words of the device generator:
+ * in holds count groups of 6 words (counter c0..c3, key k0, k1), out receives
+ * count groups of 4 output words.  Both device pointers.  Asynchronous.
+ */
+int rsvd_philox4x32_10(const uint32_t* in, uint32_t* out, int64_t count, void* stream);
+
+/* ---------------------------------------------------------------- batches
+ * A plan holds many independent problems of arbitrary, uneven sizes (for
+ * example the symmetry sectors of one compression, paper Sec. III.A) and runs
+ * them all with one batched launch per phase, optionally captured once into a
+ * HIP graph so that an execute is one graph launch. */
+typedef struct {
+    int64_t m, n, lda, k, p, q;
+    uint64_t seed;
+    double delta_trunc;
+    int64_t ldu;  /* 0 means k (after clamping) */
+    int64_t ldvt; /* 0 means n */
+} rsvd_problem_t;
+
+typedef struct rsvd_plan rsvd_plan_t;
+
+#define RSVD_PLAN_FULLSVD 1u /* the plan runs fullsvd_truncate instead of the RSVD (p, q, seed ignored) */
+#define RSVD_PLAN_GRAPH 2u   /* capture the launch sequence into a HIP graph on first execute */
+#define RSVD_PLAN_SAVE 4u    /* keep every intermediate basis for rsvd_plan_backward */
+
+/* Validates the problems, sizes and allocates the plan's device workspace.
+ * Returns RSVD_ERR_INVALID for bad problem descriptions. */
+int rsvd_plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsvd_prec_t prec,
+                     unsigned flags, rsvd_plan_t** plan);
+
+/* Runs every problem of the plan, asynchronously on stream.
+ *   A, U, S, VT  host arrays of batch device pointers (dtype of the plan)
+ *   discarded_weight  device double[batch]; k_kept device int64_t[batch];
+ *   info  device int[batch] receiving each problem's status (RSVD_OK,
+ *         RSVD_ERR_NONFINITE or RSVD_ERR_NOCONV).
+ * The pointer arrays are read during the call; the device buffers must stay
+ * valid until the stream reaches the end of the launch.  Returns RSVD_OK or a
+ * launch-level error. */
+int rsvd_plan_execute(rsvd_plan_t* plan, const void* const* A, void* const* U, void* const* S,
+                      void* const* VT, double* discarded_weight, int64_t* k_kept, int* info,
+                      void* stream);
+
+/* Device bytes of the plan's workspace. */
+int64_t rsvd_plan_workspace_bytes(const rsvd_plan_t* plan);
+
+/* Releases the plan's device memory and graph.  Safe on NULL. */
+void rsvd_plan_destroy(rsvd_plan_t* plan);
+
+/* Thread-local description of the most recent failure ("" if none). */
+const char* rsvd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBRSVD_H */

@@ -1,0 +1,8 @@
+"""librsvd for AMD MI355X: randomized truncated SVD (RSVD) and full-SVD truncation.
+
+The heavy lifting is in the HIP library librsvd.so (include/librsvd.h); this
+package only marshals arguments and owns torch-allocated outputs.
+"""
+from .rsvd import Plan, fullsvd_truncate, rsvd_truncate  # noqa: F401
+
+__all__ = ["rsvd_truncate", "fullsvd_truncate", "Plan"]

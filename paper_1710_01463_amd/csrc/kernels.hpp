@@ -1,0 +1,170 @@
+// Host-visible kernel descriptors and launchers of librsvd.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsvd {
+
+// One GEMM of a batched launch:  C (M x N) [+]= op(A) (M x K) * op(X) (K x N)
+//   op(A)(i, t) = transA ? A[t*lda + i] : A[i*lda + t]
+//   op(X)(t, j) = transX ? X[g(j)*ldx + t] : X[t*ldx + j],  g(j) = gather ? gather[j] : j
+//   C written at C[i*ldc + j] (transC = 0) or C[j*ldc + i] (transC = 1).
+// skip: when non-null and *skip != 0 the problem is left untouched.
+struct GemmDesc {
+    const void* A;
+    const void* X;
+    void* C;
+    const int* gather;
+    const int* skip;
+    int64_t lda, ldx, ldc;
+    int M, N, K;
+    int transA, transX, transC;
+    int accumulate;
+    int tiles_n;
+    int pad_;
+};
+
+// Storage kinds of the operands of a GEMM launch and the MFMA used.
+enum GemmKind : int {
+    GK_F64 = 0,   // FP64 MFMA 16x16x4, operands converted to double on load
+    GK_F32 = 1,   // FP32 MFMA 16x16x4, operands converted to float on load
+    GK_BF16 = 2,  // BF16 MFMA 16x16x32 (FP32 accumulate), operands rounded to bf16 on load
+};
+
+enum Elem : int { E_F64 = 0, E_F32 = 1, E_BF16 = 2 };
+
+constexpr int GEMM_BM = 64;
+constexpr int GEMM_BN = 64;
+
+// descs: device array of nprob descriptors; tile_begin: device array of nprob+1 prefix
+// sums of per-problem tile counts (ceil(M/64) * ceil(N/64)).
+hipError_t launch_gemm(GemmKind kind, Elem ea, Elem ex, Elem ec, const GemmDesc* descs,
+                       const int* tile_begin, int nprob, int total_tiles, hipStream_t stream);
+
+// ---------------------------------------------------------------- QR (orthonormalisation)
+// One orthonormalisation of a (rows x l) matrix M into Qout (rows x l, FP64),
+// by Cholesky QR (Gram G = M^T M, G = L L^T, Qout = M L^-T) with a Householder
+// fallback.  Buffers are per problem.
+struct QrDesc {
+    const void* Min;   // rows x l, row-major, ld = l
+    double* Qout;      // rows x l, ld = l
+    double* G;         // l x l Gram
+    double* L;         // l x l Cholesky factor (lower)
+    int* flag;         // breakdown flag: set to 1 when Cholesky QR cannot be used
+    int rows, l;
+    int min_elem;      // Elem of Min
+    int pad_;
+};
+
+// Cholesky of G into L; sets *flag on breakdown.  max_l: largest l of the batch.
+constexpr int CHOL_MAX_L = 1024;
+hipError_t launch_chol(const QrDesc* d, int nprob, int max_l, hipStream_t s);
+// Qout = src * L^-T where src = Min (from_min = 1) or Qout itself (from_min = 0, in place).
+// row_begin: prefix sums of ceil(rows / 16) per problem.
+hipError_t launch_trsm(const QrDesc* d, const int* row_begin, int nprob, int total_blocks, int from_min,
+                       int max_l, hipStream_t s);
+// Raises the dynamic-LDS limit of the Cholesky and substitution kernels.
+hipError_t init_qr_kernels();
+// Householder QR of Min into Qout for the problems whose flag is set.
+hipError_t launch_householder(const QrDesc* d, int nprob, hipStream_t s);
+
+// ---------------------------------------------------------------- block one-sided Jacobi
+// Orthogonalises the R rows of X (R x C, row-major, R <= C) by left rotations,
+// accumulating them in P (R x R).  Rows are grouped in blocks of 16; the nb
+// blocks (nb even) are paired by the round-robin schedule, one round per
+// launch.
+struct JacDesc {
+    double* X;
+    double* P;
+    int* rot;          // per-sweep "rotated" flags, max_sweeps entries
+    int64_t ldx, ldp;
+    int R, C, nb;
+    int pad_;
+    double tol;
+};
+constexpr int JAC_B = 16;
+hipError_t launch_jacobi_round(const JacDesc* d, const int* pair_begin, int nprob, int total_pairs,
+                               int sweep, int round, hipStream_t s);
+
+// ---------------------------------------------------------------- finishing
+// mode 0: RSVD (X = B rows, w from ||A||^2 - sum), mode 1: full SVD with X = A,
+// mode 2: full SVD with X = A^T.  Writes sigma, perm, S, VT (mode 0,1) or U
+// (mode 2 from X; mode 1 from P), discarded weight, k_kept and info.
+struct FinDesc {
+    const double* X;
+    const double* P;
+    double* sig;       // R
+    int* perm;         // R
+    const double* normA2;
+    const int* rot;    // Jacobi flags, to detect the sweep cap
+    void* U;
+    void* S;
+    void* VT;
+    double* w_out;
+    int64_t* kkept_out;
+    int* info_out;
+    int64_t ldx, ldp, ldu, ldvt;
+    int R, C, m, n, k;
+    int mode;
+    int max_sweeps;
+    int pad_;
+    double delta;
+};
+hipError_t launch_finish(const FinDesc* d, int nprob, int out_f64, hipStream_t s);
+// Zero columns >= k_kept of U and make the largest-magnitude entry of every kept
+// left vector positive (flipping the matching row of VT).  col_begin: prefix of k.
+hipError_t launch_signfix(const FinDesc* d, const int* col_begin, int nprob, int total_cols,
+                          int out_f64, hipStream_t s);
+
+// ---------------------------------------------------------------- staging
+// ||A||_F^2 (deterministic two-level FP64 reduction) and optional cast of A.
+struct StageDesc {
+    const void* A;
+    void* Acast;       // may be null
+    double* partial;   // one per row chunk
+    double* normA2;
+    int64_t lda;
+    int m, n;
+    int a_elem, cast_elem;
+    int chunk_begin, nchunks;
+};
+constexpr int STAGE_ROWS = 8;
+hipError_t launch_stage(const StageDesc* d, const int* chunk_begin, int nprob, int total_chunks,
+                        hipStream_t s);
+hipError_t launch_stage_final(const StageDesc* d, int nprob, hipStream_t s);
+
+// Gaussian test matrix Omega (n x l) of every problem, element type elem.
+struct OmegaDesc {
+    void* Om;
+    uint64_t seed;
+    int n, l;
+    int elem;
+    int pad_;
+};
+hipError_t launch_omega(const OmegaDesc* d, const int* blk_begin, int nprob, int total_blocks,
+                        hipStream_t s);
+
+hipError_t launch_philox_words(const uint32_t* in, uint32_t* out, int64_t count, hipStream_t s);
+
+// Fill helpers (graph-safe replacements for memset).
+hipError_t launch_fill_i32(int* p, int value, int64_t count, hipStream_t s);
+// Copy A (m x n, lda, any elem) into X as FP64, transposed or not, for the full SVD.
+struct CopyDesc {
+    const void* A;
+    double* X;
+    int64_t lda, ldx;
+    int m, n;
+    int a_elem, transpose;
+};
+hipError_t launch_copy_f64(const CopyDesc* d, const int* blk_begin, int nprob, int total_blocks,
+                           hipStream_t s);
+// P = identity (R x R) for every problem.
+struct EyeDesc {
+    double* P;
+    int64_t ldp;
+    int R;
+    int pad_;
+};
+hipError_t launch_eye(const EyeDesc* d, const int* blk_begin, int nprob, int total_blocks, hipStream_t s);
+
+}  // namespace rsvd

@@ -1,0 +1,896 @@
+// Host side of librsvd: problem validation, workspace layout, descriptor
+// tables, the launch sequence of the RSVD (paper Sec. II.B, Alg. RSVD) and of
+// the full-SVD truncation (Sec. II.A, Alg. TSVD), HIP-graph capture, the
+// one-shot plan cache and the C ABI declared in include/librsvd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/librsvd.h"
+#include "kernels.hpp"
+
+using namespace rsvd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                                   \
+    do {                                                                                            \
+        hipError_t e_ = (x);                                                                        \
+        if (e_ != hipSuccess) return fail(RSVD_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int JAC_MAX_SWEEPS = 30;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int elem_bytes(Elem e) { return e == E_F64 ? 8 : (e == E_F32 ? 4 : 2); }
+
+// Byte blob holding every descriptor table and prefix array of a plan; the
+// same layout is rebuilt for every execute, only pointers and scalars change.
+struct Blob {
+    std::vector<char> bytes;
+    template <typename T> size_t add(const std::vector<T>& v)
+    {
+        size_t off = align_up(bytes.size(), 64);
+        bytes.resize(off + v.size() * sizeof(T));
+        if (!v.empty()) memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+        return off;
+    }
+};
+
+struct ProbHost {
+    int64_t m, n, lda, k, p, q, ldu, ldvt;
+    uint64_t seed;
+    double delta;
+    int l;       // sketch width
+    int R, C;    // Jacobi rows / columns
+    int nb;      // Jacobi blocks (even)
+    int mode;    // finish mode
+    // workspace offsets (bytes)
+    size_t o_acast, o_om, o_m[2], o_q[2], o_g, o_l1, o_l2, o_b, o_p, o_sig, o_perm, o_norm, o_part,
+        o_flags, o_rot, o_info_local;
+    std::vector<size_t> o_mstage, o_qstage, o_l1stage, o_l2stage;
+    int nchunks;
+};
+
+struct GemmLaunch {
+    GemmKind kind;
+    Elem ea, ex, ec;
+    size_t off_desc, off_begin;
+    int total;
+};
+struct IdxLaunch {
+    size_t off_desc, off_begin;
+    int total;
+};
+
+}  // namespace
+
+struct rsvd_plan {
+    int nprob = 0;
+    rsvd_dtype_t dt = RSVD_F64;
+    rsvd_prec_t prec = RSVD_PREC_F64;
+    unsigned flags = 0;
+    bool fullsvd = false;
+    std::vector<ProbHost> probs;
+    int max_l = 0, max_nb = 2, max_q = 0;
+    Elem e_store = E_F64, e_sketch = E_F64, e_y = E_F64;
+    bool need_cast = false;
+    size_t ws_bytes = 0;
+    char* ws = nullptr;
+    size_t off_one = 0;  // an int that is always 1 (static skip)
+    // descriptor blob
+    Blob hb;
+    char* dblob = nullptr;
+    char* hblob_pinned = nullptr;
+    size_t blob_bytes = 0;
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
+    // recorded launch layout (offsets into the blob)
+    IdxLaunch stage, omega, copy, eye, finish, signfix;
+    std::vector<GemmLaunch> g_sketch, g_gram1, g_gram2;
+    std::vector<IdxLaunch> qr, trsm;
+    GemmLaunch g_b, g_u;
+    IdxLaunch jac;
+    int total_flags = 0;
+    size_t off_flags_base = 0;
+    // last pointers used to build the blob
+    std::vector<const void*> lastA;
+    std::vector<void*> lastU, lastS, lastVT;
+    double* lastW = nullptr;
+    int64_t* lastK = nullptr;
+    int* lastInfo = nullptr;
+    bool blob_valid = false;
+    // graph
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+int validate_problem(const rsvd_problem_t& p, bool fullsvd)
+{
+    if (p.m < 1 || p.n < 1 || p.k < 1) return fail(RSVD_ERR_INVALID, "m, n and k must be >= 1");
+    if (p.m > (1 << 24) || p.n > (1 << 24)) return fail(RSVD_ERR_INVALID, "m or n too large");
+    if (p.lda < p.n) return fail(RSVD_ERR_INVALID, "lda < n");
+    if (!fullsvd && (p.p < 0 || p.q < 0)) return fail(RSVD_ERR_INVALID, "p and q must be >= 0");
+    if (!fullsvd && p.q > 64) return fail(RSVD_ERR_INVALID, "q > 64");
+    if (!(p.delta_trunc >= 0.0)) return fail(RSVD_ERR_INVALID, "delta_trunc must be >= 0 and not NaN");
+    int64_t mn = std::min(p.m, p.n);
+    int64_t kk = std::min(p.k, mn);
+    if (p.ldu != 0 && p.ldu < kk) return fail(RSVD_ERR_INVALID, "ldu < k");
+    if (p.ldvt != 0 && p.ldvt < p.n) return fail(RSVD_ERR_INVALID, "ldvt < n");
+    if (fullsvd && mn > 2048) return fail(RSVD_ERR_INVALID, "full SVD supports min(m, n) <= 2048");
+    if (!fullsvd) {
+        int64_t l = std::min(kk + p.p, mn);
+        if (l > 1024) return fail(RSVD_ERR_INVALID, "k + p must be <= 1024");
+    }
+    return RSVD_OK;
+}
+
+Elem store_elem(rsvd_dtype_t dt) { return dt == RSVD_F64 ? E_F64 : E_F32; }
+
+// ---------------------------------------------------------------- workspace layout
+void layout(rsvd_plan& P)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1), 256);
+        return o;
+    };
+    P.off_one = take(sizeof(int));
+    const bool save = (P.flags & RSVD_PLAN_SAVE) != 0;
+    P.total_flags = 0;
+    for (auto& h : P.probs) {
+        const int64_t m = h.m, n = h.n, l = h.l;
+        h.nchunks = (int)((m + STAGE_ROWS - 1) / STAGE_ROWS);
+        h.o_norm = take(sizeof(double));
+        h.o_part = take(sizeof(double) * h.nchunks);
+        h.o_sig = take(sizeof(double) * h.R);
+        h.o_perm = take(sizeof(int) * h.R);
+        h.o_p = take(sizeof(double) * (size_t)h.R * h.R);
+        h.o_info_local = take(sizeof(int));
+        if (P.fullsvd) {
+            h.o_b = take(sizeof(double) * (size_t)h.R * h.C);
+            continue;
+        }
+        h.o_acast = P.need_cast ? take((size_t)elem_bytes(P.e_sketch) * m * n) : 0;
+        h.o_om = take((size_t)elem_bytes(P.e_sketch) * n * l);
+        const int nst = (int)(2 * h.q + 1);
+        h.o_mstage.assign(nst, 0);
+        h.o_qstage.assign(nst, 0);
+        h.o_l1stage.assign(nst, 0);
+        h.o_l2stage.assign(nst, 0);
+        size_t shared_m[2], shared_q[2], sl1 = 0, sl2 = 0;
+        if (!save) {
+            shared_m[0] = take((size_t)elem_bytes(P.e_y) * m * l);
+            shared_m[1] = take((size_t)elem_bytes(P.e_y) * n * l);
+            shared_q[0] = take(sizeof(double) * m * l);
+            shared_q[1] = take(sizeof(double) * n * l);
+            sl1 = take(sizeof(double) * l * l);
+            sl2 = take(sizeof(double) * l * l);
+        }
+        for (int s = 0; s < nst; ++s) {
+            const int64_t rows = (s % 2 == 0) ? m : n;
+            if (save) {
+                h.o_mstage[s] = take((size_t)elem_bytes(P.e_y) * rows * l);
+                h.o_qstage[s] = take(sizeof(double) * rows * l);
+                h.o_l1stage[s] = take(sizeof(double) * l * l);
+                h.o_l2stage[s] = take(sizeof(double) * l * l);
+            } else {
+                h.o_mstage[s] = shared_m[s % 2];
+                h.o_qstage[s] = shared_q[s % 2];
+                h.o_l1stage[s] = sl1;
+                h.o_l2stage[s] = sl2;
+            }
+        }
+        h.o_g = take(sizeof(double) * l * l);
+        h.o_b = take(sizeof(double) * (size_t)h.R * h.C);
+    }
+    // flags: per problem (2 q_max + 1) QR flags followed by JAC_MAX_SWEEPS rot flags
+    P.off_flags_base = take(0);
+    const int per = (int)(2 * P.max_q + 1) + JAC_MAX_SWEEPS;
+    for (size_t b = 0; b < P.probs.size(); ++b) {
+        P.probs[b].o_flags = P.off_flags_base + sizeof(int) * (size_t)per * b;
+        P.probs[b].o_rot = P.probs[b].o_flags + sizeof(int) * (size_t)(2 * P.max_q + 1);
+    }
+    P.total_flags = per * (int)P.probs.size();
+    off = align_up(P.off_flags_base + sizeof(int) * (size_t)P.total_flags, 256);
+    P.ws_bytes = off;
+}
+
+template <typename T> T* wsp(const rsvd_plan& P, size_t off) { return (T*)(P.ws + off); }
+
+int tiles_of(int M, int N) { return ((M + GEMM_BM - 1) / GEMM_BM) * ((N + GEMM_BN - 1) / GEMM_BN); }
+
+GemmLaunch add_gemm(Blob& B, GemmKind kind, Elem ea, Elem ex, Elem ec, std::vector<GemmDesc>& descs)
+{
+    std::vector<int> begin(descs.size() + 1, 0);
+    for (size_t b = 0; b < descs.size(); ++b) {
+        GemmDesc& d = descs[b];
+        int t = 0;
+        if (d.M > 0 && d.N > 0 && d.K >= 0 && d.A != nullptr) t = tiles_of(d.M, d.N);
+        d.tiles_n = (d.N + GEMM_BN - 1) / GEMM_BN;
+        begin[b + 1] = begin[b] + t;
+    }
+    GemmLaunch g;
+    g.kind = kind;
+    g.ea = ea;
+    g.ex = ex;
+    g.ec = ec;
+    g.off_desc = B.add(descs);
+    g.off_begin = B.add(begin);
+    g.total = begin.back();
+    return g;
+}
+
+template <typename D> IdxLaunch add_idx(Blob& B, const std::vector<D>& descs, const std::vector<int>& counts)
+{
+    std::vector<int> begin(counts.size() + 1, 0);
+    for (size_t b = 0; b < counts.size(); ++b) begin[b + 1] = begin[b] + counts[b];
+    IdxLaunch L;
+    L.off_desc = B.add(descs);
+    L.off_begin = B.add(begin);
+    L.total = begin.back();
+    return L;
+}
+
+GemmDesc gd(const void* A, int64_t lda, int transA, const void* X, int64_t ldx, int transX, void* C,
+            int64_t ldc, int M, int N, int K, const int* skip = nullptr, const int* gather = nullptr)
+{
+    GemmDesc d;
+    memset(&d, 0, sizeof(d));
+    d.A = A;
+    d.lda = lda;
+    d.transA = transA;
+    d.X = X;
+    d.ldx = ldx;
+    d.transX = transX;
+    d.C = C;
+    d.ldc = ldc;
+    d.M = M;
+    d.N = N;
+    d.K = K;
+    d.skip = skip;
+    d.gather = gather;
+    return d;
+}
+
+// Builds every descriptor table for the given user pointers.
+void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const* S, void* const* VT,
+                double* w, int64_t* kk, int* info)
+{
+    Blob B;
+    const int np = P.nprob;
+    const int* one = wsp<int>(P, P.off_one);
+    const Elem es = P.e_store;
+    const int out_f64 = (P.dt == RSVD_F64);
+    (void)out_f64;
+
+    // staging: ||A||^2 and the optional cast
+    {
+        std::vector<StageDesc> d(np);
+        std::vector<int> cnt(np);
+        for (int b = 0; b < np; ++b) {
+            const ProbHost& h = P.probs[b];
+            StageDesc& s = d[b];
+            memset(&s, 0, sizeof(s));
+            s.A = A[b];
+            s.Acast = (!P.fullsvd && P.need_cast) ? (void*)wsp<char>(P, h.o_acast) : nullptr;
+            s.partial = wsp<double>(P, h.o_part);
+            s.normA2 = wsp<double>(P, h.o_norm);
+            s.lda = h.lda;
+            s.m = (int)h.m;
+            s.n = (int)h.n;
+            s.a_elem = es;
+            s.cast_elem = P.e_sketch;
+            s.nchunks = h.nchunks;
+            cnt[b] = h.nchunks;
+        }
+        P.stage = add_idx(B, d, cnt);
+    }
+    if (!P.fullsvd) {
+        // Gaussian test matrices
+        {
+            std::vector<OmegaDesc> d(np);
+            std::vector<int> cnt(np);
+            for (int b = 0; b < np; ++b) {
+                const ProbHost& h = P.probs[b];
+                OmegaDesc& o = d[b];
+                memset(&o, 0, sizeof(o));
+                o.Om = wsp<char>(P, h.o_om);
+                o.seed = h.seed;
+                o.n = (int)h.n;
+                o.l = h.l;
+                o.elem = P.e_sketch;
+                const int64_t pairs = ((h.n + 1) / 2) * (int64_t)h.l;
+                cnt[b] = (int)((pairs + 255) / 256);
+            }
+            P.omega = add_idx(B, d, cnt);
+        }
+        const GemmKind gk = P.prec == RSVD_PREC_F64 ? GK_F64 : (P.prec == RSVD_PREC_F32 ? GK_F32 : GK_BF16);
+        const Elem ea_sk = P.need_cast ? P.e_sketch : es;
+        const int nst = 2 * P.max_q + 1;
+        P.g_sketch.clear();
+        P.g_gram1.clear();
+        P.g_gram2.clear();
+        P.qr.clear();
+        P.trsm.clear();
+        for (int s = 0; s < nst; ++s) {
+            std::vector<GemmDesc> dsk(np), dg1(np), dg2(np);
+            std::vector<QrDesc> dq(np);
+            std::vector<int> rowblk(np);
+            for (int b = 0; b < np; ++b) {
+                const ProbHost& h = P.probs[b];
+                const int l = h.l;
+                const bool active = s <= 2 * h.q;
+                const int64_t rows = (s % 2 == 0) ? h.m : h.n;
+                const void* Aop = P.need_cast ? (const void*)wsp<char>(P, h.o_acast) : A[b];
+                const int64_t lda_op = P.need_cast ? h.n : h.lda;
+                void* M = active ? (void*)wsp<char>(P, h.o_mstage[s]) : nullptr;
+                double* Qs = active ? wsp<double>(P, h.o_qstage[s]) : nullptr;
+                int* flag = wsp<int>(P, h.o_flags) + s;
+                if (!active) {
+                    dsk[b] = gd(nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0, 0, 0, one);
+                    dg1[b] = dsk[b];
+                    dg2[b] = dsk[b];
+                    memset(&dq[b], 0, sizeof(QrDesc));
+                    dq[b].flag = const_cast<int*>(one);
+                    dq[b].l = l;
+                    rowblk[b] = 0;
+                    continue;
+                }
+                if (s == 0) {
+                    dsk[b] = gd(Aop, lda_op, 0, wsp<char>(P, h.o_om), l, 0, M, l, (int)h.m, l, (int)h.n);
+                } else if (s % 2 == 1) {
+                    dsk[b] = gd(Aop, lda_op, 1, wsp<double>(P, h.o_qstage[s - 1]), l, 0, M, l, (int)h.n, l,
+                                (int)h.m);
+                } else {
+                    dsk[b] = gd(Aop, lda_op, 0, wsp<double>(P, h.o_qstage[s - 1]), l, 0, M, l, (int)h.m, l,
+                                (int)h.n);
+                }
+                double* G = wsp<double>(P, h.o_g);
+                dg1[b] = gd(M, l, 1, M, l, 0, G, l, l, l, (int)rows, flag);
+                dg2[b] = gd(Qs, l, 1, Qs, l, 0, G, l, l, l, (int)rows, flag);
+                QrDesc& q = dq[b];
+                memset(&q, 0, sizeof(q));
+                q.Min = M;
+                q.Qout = Qs;
+                q.G = G;
+                q.L = wsp<double>(P, h.o_l1stage[s]);
+                q.flag = flag;
+                q.rows = (int)rows;
+                q.l = l;
+                q.min_elem = P.e_y;
+                rowblk[b] = (int)((rows + 15) / 16);
+            }
+            // X operand element of the sketch GEMMs: Omega at s = 0, FP64 bases afterwards
+            P.g_sketch.push_back(add_gemm(B, gk, ea_sk, s == 0 ? P.e_sketch : E_F64, P.e_y, dsk));
+            P.g_gram1.push_back(add_gemm(B, GK_F64, P.e_y, P.e_y, E_F64, dg1));
+            P.g_gram2.push_back(add_gemm(B, GK_F64, E_F64, E_F64, E_F64, dg2));
+            std::vector<int> ones(np, 1);
+            P.qr.push_back(add_idx(B, dq, ones));
+            // second Cholesky pass writes L2: separate descriptor copy
+            std::vector<QrDesc> dq2 = dq;
+            for (int b = 0; b < np; ++b)
+                if (s <= 2 * P.probs[b].q) dq2[b].L = wsp<double>(P, P.probs[b].o_l2stage[s]);
+            P.qr.push_back(add_idx(B, dq2, ones));
+            P.trsm.push_back(add_idx(B, dq, rowblk));
+            P.trsm.push_back(add_idx(B, dq2, rowblk));
+        }
+        // B = Q^T A in FP64 from the stored A
+        {
+            std::vector<GemmDesc> d(np);
+            for (int b = 0; b < np; ++b) {
+                const ProbHost& h = P.probs[b];
+                const double* Qf = wsp<double>(P, h.o_qstage[2 * h.q]);
+                d[b] = gd(Qf, h.l, 1, A[b], h.lda, 0, wsp<double>(P, h.o_b), h.n, h.l, (int)h.n, (int)h.m);
+            }
+            P.g_b = add_gemm(B, GK_F64, E_F64, es, E_F64, d);
+        }
+    } else {
+        std::vector<CopyDesc> d(np);
+        std::vector<int> cnt(np);
+        for (int b = 0; b < np; ++b) {
+            const ProbHost& h = P.probs[b];
+            CopyDesc& c = d[b];
+            memset(&c, 0, sizeof(c));
+            c.A = A[b];
+            c.X = wsp<double>(P, h.o_b);
+            c.lda = h.lda;
+            c.ldx = h.C;
+            c.m = (int)h.m;
+            c.n = (int)h.n;
+            c.a_elem = es;
+            c.transpose = (h.m > h.n) ? 1 : 0;
+            cnt[b] = (int)(((h.m + 63) / 64) * ((h.n + 63) / 64));
+        }
+        P.copy = add_idx(B, d, cnt);
+    }
+    // Jacobi
+    {
+        std::vector<EyeDesc> de(np);
+        std::vector<int> ce(np);
+        std::vector<JacDesc> dj(np);
+        std::vector<int> cj(np);
+        for (int b = 0; b < np; ++b) {
+            const ProbHost& h = P.probs[b];
+            EyeDesc& e = de[b];
+            memset(&e, 0, sizeof(e));
+            e.P = wsp<double>(P, h.o_p);
+            e.ldp = h.R;
+            e.R = h.R;
+            ce[b] = (int)(((int64_t)h.R * h.R + 255) / 256);
+            JacDesc& j = dj[b];
+            memset(&j, 0, sizeof(j));
+            j.X = wsp<double>(P, h.o_b);
+            j.P = wsp<double>(P, h.o_p);
+            j.rot = wsp<int>(P, h.o_rot);
+            j.ldx = h.C;
+            j.ldp = h.R;
+            j.R = h.R;
+            j.C = h.C;
+            j.nb = h.nb;
+            j.tol = (double)h.C * std::ldexp(1.0, -53);
+            cj[b] = h.nb / 2;
+        }
+        P.eye = add_idx(B, de, ce);
+        P.jac = add_idx(B, dj, cj);
+    }
+    // finish + sign fix
+    {
+        std::vector<FinDesc> d(np);
+        std::vector<int> ones(np, 1), cols(np);
+        for (int b = 0; b < np; ++b) {
+            const ProbHost& h = P.probs[b];
+            FinDesc& f = d[b];
+            memset(&f, 0, sizeof(f));
+            f.X = wsp<double>(P, h.o_b);
+            f.P = wsp<double>(P, h.o_p);
+            f.sig = wsp<double>(P, h.o_sig);
+            f.perm = wsp<int>(P, h.o_perm);
+            f.normA2 = wsp<double>(P, h.o_norm);
+            f.rot = wsp<int>(P, h.o_rot);
+            f.U = U[b];
+            f.S = S[b];
+            f.VT = VT[b];
+            f.w_out = w + b;
+            f.kkept_out = kk + b;
+            f.info_out = info ? info + b : wsp<int>(P, h.o_info_local);
+            f.ldx = h.C;
+            f.ldp = h.R;
+            f.ldu = h.ldu;
+            f.ldvt = h.ldvt;
+            f.R = h.R;
+            f.C = h.C;
+            f.m = (int)h.m;
+            f.n = (int)h.n;
+            f.k = (int)h.k;
+            f.mode = h.mode;
+            f.max_sweeps = JAC_MAX_SWEEPS;
+            f.delta = h.delta;
+            cols[b] = (int)h.k;
+        }
+        P.finish = add_idx(B, d, ones);
+        P.signfix = add_idx(B, d, cols);
+    }
+    if (!P.fullsvd) {
+        // U = Q Utilde[:, perm[:k]],  Utilde = P^T  ->  U(:, j) = Q P(perm[j], :)^T
+        std::vector<GemmDesc> d(np);
+        for (int b = 0; b < np; ++b) {
+            const ProbHost& h = P.probs[b];
+            const double* Qf = wsp<double>(P, h.o_qstage[2 * h.q]);
+            d[b] = gd(Qf, h.l, 0, wsp<double>(P, h.o_p), h.l, 1, U[b], h.ldu, (int)h.m, (int)h.k, h.l,
+                      nullptr, wsp<int>(P, h.o_perm));
+        }
+        P.g_u = add_gemm(B, GK_F64, E_F64, E_F64, P.dt == RSVD_F64 ? E_F64 : E_F32, d);
+    }
+    P.hb = std::move(B);
+}
+
+#define LCHK(x)                                                                                   \
+    do {                                                                                          \
+        hipError_t e_ = (x);                                                                      \
+        if (e_ != hipSuccess) return fail(RSVD_ERR_HIP, std::string("launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T> const T* dp(const rsvd_plan& P, size_t off) { return (const T*)(P.dblob + off); }
+
+int gemm(const rsvd_plan& P, const GemmLaunch& g, hipStream_t s)
+{
+    LCHK(launch_gemm(g.kind, g.ea, g.ex, g.ec, dp<GemmDesc>(P, g.off_desc), dp<int>(P, g.off_begin), P.nprob,
+                     g.total, s));
+    return RSVD_OK;
+}
+
+// The full launch sequence of one execute (captured into a graph when asked).
+int enqueue(rsvd_plan& P, hipStream_t s)
+{
+    const int np = P.nprob;
+    const int out_f64 = P.dt == RSVD_F64;
+    LCHK(launch_fill_i32(wsp<int>(P, P.off_one), 1, 1, s));
+    LCHK(launch_fill_i32(wsp<int>(P, P.off_flags_base), 0, P.total_flags, s));
+    LCHK(launch_stage(dp<StageDesc>(P, P.stage.off_desc), dp<int>(P, P.stage.off_begin), np, P.stage.total, s));
+    LCHK(launch_stage_final(dp<StageDesc>(P, P.stage.off_desc), np, s));
+    if (!P.fullsvd) {
+        LCHK(launch_omega(dp<OmegaDesc>(P, P.omega.off_desc), dp<int>(P, P.omega.off_begin), np, P.omega.total,
+                          s));
+        const int nst = 2 * P.max_q + 1;
+        for (int st = 0; st < nst; ++st) {
+            int rc;
+            if ((rc = gemm(P, P.g_sketch[st], s)) != RSVD_OK) return rc;
+            // Cholesky QR pass 1
+            if ((rc = gemm(P, P.g_gram1[st], s)) != RSVD_OK) return rc;
+            const IdxLaunch& q1 = P.qr[2 * st];
+            const IdxLaunch& q2 = P.qr[2 * st + 1];
+            const IdxLaunch& t1 = P.trsm[2 * st];
+            const IdxLaunch& t2 = P.trsm[2 * st + 1];
+            LCHK(launch_chol(dp<QrDesc>(P, q1.off_desc), np, P.max_l, s));
+            LCHK(launch_trsm(dp<QrDesc>(P, t1.off_desc), dp<int>(P, t1.off_begin), np, t1.total, 1, P.max_l, s));
+            // pass 2 on the result of pass 1
+            if ((rc = gemm(P, P.g_gram2[st], s)) != RSVD_OK) return rc;
+            LCHK(launch_chol(dp<QrDesc>(P, q2.off_desc), np, P.max_l, s));
+            LCHK(launch_trsm(dp<QrDesc>(P, t2.off_desc), dp<int>(P, t2.off_begin), np, t2.total, 0, P.max_l, s));
+            // Householder for the problems whose Cholesky QR broke down
+            LCHK(launch_householder(dp<QrDesc>(P, q1.off_desc), np, s));
+        }
+        int rc;
+        if ((rc = gemm(P, P.g_b, s)) != RSVD_OK) return rc;
+    } else {
+        LCHK(launch_copy_f64(dp<CopyDesc>(P, P.copy.off_desc), dp<int>(P, P.copy.off_begin), np, P.copy.total, s));
+    }
+    LCHK(launch_eye(dp<EyeDesc>(P, P.eye.off_desc), dp<int>(P, P.eye.off_begin), np, P.eye.total, s));
+    for (int sw = 0; sw < JAC_MAX_SWEEPS; ++sw)
+        for (int r = 0; r < P.max_nb - 1; ++r)
+            LCHK(launch_jacobi_round(dp<JacDesc>(P, P.jac.off_desc), dp<int>(P, P.jac.off_begin), np, P.jac.total,
+                                     sw, r, s));
+    LCHK(launch_finish(dp<FinDesc>(P, P.finish.off_desc), np, out_f64, s));
+    if (!P.fullsvd) {
+        int rc;
+        if ((rc = gemm(P, P.g_u, s)) != RSVD_OK) return rc;
+    }
+    LCHK(launch_signfix(dp<FinDesc>(P, P.signfix.off_desc), dp<int>(P, P.signfix.off_begin), np,
+                        P.signfix.total, out_f64, s));
+    return RSVD_OK;
+}
+
+void plan_free(rsvd_plan* P)
+{
+    if (!P) return;
+    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+    if (P->upload_done) (void)hipEventDestroy(P->upload_done);
+    if (P->ws) (void)hipFree(P->ws);
+    if (P->dblob) (void)hipFree(P->dblob);
+    if (P->hblob_pinned) (void)hipHostFree(P->hblob_pinned);
+    delete P;
+}
+
+int plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsvd_prec_t prec, unsigned flags,
+                rsvd_plan** out)
+{
+    if (!out) return fail(RSVD_ERR_INVALID, "plan output pointer is null");
+    *out = nullptr;
+    if (!probs || batch < 1 || batch > (1 << 20)) return fail(RSVD_ERR_INVALID, "batch must be in [1, 2^20]");
+    if (dt != RSVD_F64 && dt != RSVD_F32) return fail(RSVD_ERR_INVALID, "unknown dtype");
+    if (prec != RSVD_PREC_F64 && prec != RSVD_PREC_F32 && prec != RSVD_PREC_BF16)
+        return fail(RSVD_ERR_INVALID, "unknown precision");
+    const bool fullsvd = (flags & RSVD_PLAN_FULLSVD) != 0;
+    for (int64_t b = 0; b < batch; ++b) {
+        int rc = validate_problem(probs[b], fullsvd);
+        if (rc != RSVD_OK) return fail(rc, "problem " + std::to_string(b) + ": " + g_err);
+    }
+    {
+        static std::once_flag once;
+        static hipError_t init_err = hipSuccess;
+        std::call_once(once, [] { init_err = init_qr_kernels(); });
+        if (init_err != hipSuccess)
+            return fail(RSVD_ERR_HIP, std::string("kernel attributes: ") + hipGetErrorString(init_err));
+    }
+    rsvd_plan* P = new rsvd_plan();
+    P->nprob = (int)batch;
+    P->dt = dt;
+    P->prec = fullsvd ? RSVD_PREC_F64 : prec;
+    P->flags = flags;
+    P->fullsvd = fullsvd;
+    P->e_store = store_elem(dt);
+    P->e_sketch = P->prec == RSVD_PREC_F64 ? E_F64 : (P->prec == RSVD_PREC_F32 ? E_F32 : E_BF16);
+    P->e_y = P->prec == RSVD_PREC_F64 ? E_F64 : E_F32;
+    P->need_cast = (P->prec == RSVD_PREC_BF16) || (P->prec == RSVD_PREC_F32 && dt == RSVD_F64);
+    P->probs.resize(batch);
+    for (int64_t b = 0; b < batch; ++b) {
+        const rsvd_problem_t& p = probs[b];
+        ProbHost& h = P->probs[b];
+        h.m = p.m;
+        h.n = p.n;
+        h.lda = p.lda;
+        const int64_t mn = std::min(p.m, p.n);
+        h.k = std::min(p.k, mn);
+        h.p = fullsvd ? 0 : p.p;
+        h.q = fullsvd ? 0 : p.q;
+        h.ldu = p.ldu ? p.ldu : h.k;
+        h.ldvt = p.ldvt ? p.ldvt : p.n;
+        h.seed = p.seed;
+        h.delta = p.delta_trunc;
+        if (fullsvd) {
+            h.l = (int)mn;
+            h.R = (int)mn;
+            h.C = (int)std::max(p.m, p.n);
+            h.mode = (p.m > p.n) ? 2 : 1;
+        } else {
+            h.l = (int)std::min(h.k + p.p, mn);
+            h.R = h.l;
+            h.C = (int)p.n;
+            h.mode = 0;
+        }
+        int nbk = (h.R + JAC_B - 1) / JAC_B;
+        if (nbk % 2) ++nbk;
+        if (nbk < 2) nbk = 2;
+        h.nb = nbk;
+        P->max_l = std::max(P->max_l, h.l);
+        P->max_nb = std::max(P->max_nb, h.nb);
+        P->max_q = std::max<int>(P->max_q, (int)h.q);
+    }
+    layout(*P);
+    hipError_t e = hipMalloc(&P->ws, P->ws_bytes);
+    if (e != hipSuccess) {
+        plan_free(P);
+        return fail(RSVD_ERR_ALLOC, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
+    }
+    // size the descriptor blob with placeholder pointers
+    {
+        std::vector<const void*> A(batch, (const void*)P->ws);
+        std::vector<void*> O(batch, (void*)P->ws);
+        build_blob(*P, A.data(), O.data(), O.data(), O.data(), (double*)P->ws, (int64_t*)P->ws, nullptr);
+        P->blob_bytes = P->hb.bytes.size();
+    }
+    e = hipMalloc(&P->dblob, std::max<size_t>(P->blob_bytes, 64));
+    if (e == hipSuccess) e = hipHostMalloc(&P->hblob_pinned, std::max<size_t>(P->blob_bytes, 64), 0);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->upload_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        plan_free(P);
+        return fail(RSVD_ERR_ALLOC, std::string("plan allocation: ") + hipGetErrorString(e));
+    }
+    *out = P;
+    return RSVD_OK;
+}
+
+int plan_execute(rsvd_plan* P, const void* const* A, void* const* U, void* const* S, void* const* VT, double* w,
+                 int64_t* kk, int* info, hipStream_t stream)
+{
+    if (!P) return fail(RSVD_ERR_INVALID, "plan is null");
+    if (!A || !U || !S || !VT || !w || !kk) return fail(RSVD_ERR_INVALID, "null output or input array");
+    for (int b = 0; b < P->nprob; ++b)
+        if (!A[b] || !U[b] || !S[b] || !VT[b]) return fail(RSVD_ERR_INVALID, "null matrix pointer in batch");
+    bool same = P->blob_valid && P->lastW == w && P->lastK == kk && P->lastInfo == info;
+    if (same) {
+        for (int b = 0; b < P->nprob && same; ++b)
+            same = P->lastA[b] == A[b] && P->lastU[b] == U[b] && P->lastS[b] == S[b] && P->lastVT[b] == VT[b];
+    }
+    if (!same) {
+        if (P->upload_pending) HIPCHK(hipEventSynchronize(P->upload_done));
+        build_blob(*P, A, U, S, VT, w, kk, info);
+        if (P->hb.bytes.size() != P->blob_bytes) return fail(RSVD_ERR_HIP, "descriptor layout changed");
+        memcpy(P->hblob_pinned, P->hb.bytes.data(), P->blob_bytes);
+        HIPCHK(hipMemcpyAsync(P->dblob, P->hblob_pinned, P->blob_bytes, hipMemcpyHostToDevice, stream));
+        HIPCHK(hipEventRecord(P->upload_done, stream));
+        P->upload_pending = true;
+        P->lastA.assign(A, A + P->nprob);
+        P->lastU.assign(U, U + P->nprob);
+        P->lastS.assign(S, S + P->nprob);
+        P->lastVT.assign(VT, VT + P->nprob);
+        P->lastW = w;
+        P->lastK = kk;
+        P->lastInfo = info;
+        P->blob_valid = true;
+    }
+    if (P->flags & RSVD_PLAN_GRAPH) {
+        if (!P->gexec) {
+            HIPCHK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+            int rc = enqueue(*P, P->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
+            if (rc != RSVD_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return fail(RSVD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+            P->graph = g;
+            HIPCHK(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+        }
+        HIPCHK(hipGraphLaunch(P->gexec, stream));
+        return RSVD_OK;
+    }
+    return enqueue(*P, stream);
+}
+
+// ---------------------------------------------------------------- one-shot cache
+struct CacheKey {
+    int64_t m, n, lda, k, p, q, ldu, ldvt;
+    int dt, prec, full;
+    bool operator<(const CacheKey& o) const
+    {
+        return std::tie(m, n, lda, k, p, q, ldu, ldvt, dt, prec, full) <
+               std::tie(o.m, o.n, o.lda, o.k, o.p, o.q, o.ldu, o.ldvt, o.dt, o.prec, o.full);
+    }
+};
+struct CacheEntry {
+    rsvd_plan* plan;
+    int* info;  // device int for the status
+    int device;
+};
+std::mutex g_cache_mu;
+std::map<std::pair<int, CacheKey>, CacheEntry> g_cache;
+constexpr size_t CACHE_MAX = 64;
+
+int one_shot(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t lda, int64_t k, int64_t p, int64_t q,
+             uint64_t seed, double delta, rsvd_prec_t prec, void* U, int64_t ldu, void* S, void* VT, int64_t ldvt,
+             double* w, int64_t* kk, hipStream_t stream, bool full)
+{
+    if (!A || !U || !S || !VT || !w || !kk) return fail(RSVD_ERR_INVALID, "null pointer argument");
+    rsvd_problem_t pr;
+    pr.m = m;
+    pr.n = n;
+    pr.lda = lda;
+    pr.k = k;
+    pr.p = p;
+    pr.q = q;
+    pr.seed = seed;
+    pr.delta_trunc = delta;
+    pr.ldu = ldu;
+    pr.ldvt = ldvt;
+    int rc = validate_problem(pr, full);
+    if (rc != RSVD_OK) return rc;
+    if (ldu < std::min(k, std::min(m, n))) return fail(RSVD_ERR_INVALID, "ldu < k");
+    if (ldvt < n) return fail(RSVD_ERR_INVALID, "ldvt < n");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    CacheKey key{m, n, lda, k, full ? 0 : p, full ? 0 : q, ldu, ldvt, (int)dt, full ? 0 : (int)prec, full ? 1 : 0};
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find({dev, key});
+    if (it == g_cache.end()) {
+        if (g_cache.size() >= CACHE_MAX) {
+            auto victim = g_cache.begin();
+            int cur = dev;
+            (void)hipSetDevice(victim->second.device);
+            (void)hipDeviceSynchronize();
+            plan_free(victim->second.plan);
+            (void)hipFree(victim->second.info);
+            (void)hipSetDevice(cur);
+            g_cache.erase(victim);
+        }
+        rsvd_plan* P = nullptr;
+        rc = plan_create(&pr, 1, dt, prec, RSVD_PLAN_GRAPH | (full ? RSVD_PLAN_FULLSVD : 0u), &P);
+        if (rc != RSVD_OK) return rc;
+        int* info = nullptr;
+        hipError_t e = hipMalloc(&info, sizeof(int));
+        if (e != hipSuccess) {
+            plan_free(P);
+            return fail(RSVD_ERR_ALLOC, "status allocation");
+        }
+        it = g_cache.emplace(std::make_pair(dev, key), CacheEntry{P, info, dev}).first;
+    }
+    rsvd_plan* P = it->second.plan;
+    // per-call scalars live in the descriptors: force a rebuild when they change
+    if (P->probs[0].seed != seed || P->probs[0].delta != delta) {
+        P->probs[0].seed = seed;
+        P->probs[0].delta = delta;
+        P->blob_valid = false;
+    }
+    const void* Aa[1] = {A};
+    void* Ua[1] = {U};
+    void* Sa[1] = {S};
+    void* Va[1] = {VT};
+    rc = plan_execute(P, Aa, Ua, Sa, Va, w, kk, it->second.info, stream);
+    if (rc != RSVD_OK) return rc;
+    int h_info = 0;
+    HIPCHK(hipMemcpyAsync(&h_info, it->second.info, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (h_info == RSVD_ERR_NONFINITE) return fail(RSVD_ERR_NONFINITE, "A contains NaN or Inf");
+    if (h_info == RSVD_ERR_NOCONV) return fail(RSVD_ERR_NOCONV, "Jacobi sweep cap reached");
+    return RSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rsvd_truncate(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t lda, int64_t k, int64_t p,
+                  int64_t q, uint64_t seed, double delta_trunc, rsvd_prec_t prec, void* U, int64_t ldu, void* S,
+                  void* VT, int64_t ldvt, double* discarded_weight, int64_t* k_kept, void* stream)
+{
+    g_err.clear();
+    if (dt != RSVD_F64 && dt != RSVD_F32) return fail(RSVD_ERR_INVALID, "unknown dtype");
+    if (prec != RSVD_PREC_F64 && prec != RSVD_PREC_F32 && prec != RSVD_PREC_BF16)
+        return fail(RSVD_ERR_INVALID, "unknown precision");
+    return one_shot(A, dt, m, n, lda, k, p, q, seed, delta_trunc, prec, U, ldu, S, VT, ldvt, discarded_weight,
+                    k_kept, (hipStream_t)stream, false);
+}
+
+int fullsvd_truncate(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t lda, int64_t k,
+                     double delta_trunc, void* U, int64_t ldu, void* S, void* VT, int64_t ldvt,
+                     double* discarded_weight, int64_t* k_kept, void* stream)
+{
+    g_err.clear();
+    if (dt != RSVD_F64 && dt != RSVD_F32) return fail(RSVD_ERR_INVALID, "unknown dtype");
+    return one_shot(A, dt, m, n, lda, k, 0, 0, 0, delta_trunc, RSVD_PREC_F64, U, ldu, S, VT, ldvt,
+                    discarded_weight, k_kept, (hipStream_t)stream, true);
+}
+
+int rsvd_plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsvd_prec_t prec,
+                     unsigned flags, rsvd_plan_t** plan)
+{
+    g_err.clear();
+    return plan_create(probs, batch, dt, prec, flags, plan);
+}
+
+int rsvd_plan_execute(rsvd_plan_t* plan, const void* const* A, void* const* U, void* const* S, void* const* VT,
+                      double* discarded_weight, int64_t* k_kept, int* info, void* stream)
+{
+    g_err.clear();
+    return plan_execute(plan, A, U, S, VT, discarded_weight, k_kept, info, (hipStream_t)stream);
+}
+
+int rsvd_gaussian(uint64_t seed, int64_t n, int64_t l, double* omega, void* stream)
+{
+    g_err.clear();
+    if (n < 1 || l < 1 || n > (1 << 24) || l > (1 << 24) || !omega) return fail(RSVD_ERR_INVALID, "bad size or null");
+    if ((n + 1) / 2 * l > ((int64_t)1 << 31) * 255) return fail(RSVD_ERR_INVALID, "too large");
+    OmegaDesc d;
+    memset(&d, 0, sizeof(d));
+    d.Om = omega;
+    d.seed = seed;
+    d.n = (int)n;
+    d.l = (int)l;
+    d.elem = E_F64;
+    const int64_t pairs = (n + 1) / 2 * l;
+    std::vector<int> begin = {0, (int)((pairs + 255) / 256)};
+    hipStream_t s = (hipStream_t)stream;
+    OmegaDesc* dd = nullptr;
+    int* db = nullptr;
+    HIPCHK(hipMalloc(&dd, sizeof(d)));
+    hipError_t e = hipMalloc(&db, sizeof(int) * 2);
+    if (e == hipSuccess) e = hipMemcpyAsync(dd, &d, sizeof(d), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(db, begin.data(), sizeof(int) * 2, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_omega(dd, db, 1, begin[1], s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dd);
+    if (db) (void)hipFree(db);
+    if (e != hipSuccess) return fail(RSVD_ERR_HIP, std::string("rsvd_gaussian: ") + hipGetErrorString(e));
+    return RSVD_OK;
+}
+
+int rsvd_philox4x32_10(const uint32_t* in, uint32_t* out, int64_t count, void* stream)
+{
+    g_err.clear();
+    if (count < 0 || (count > 0 && (!in || !out))) return fail(RSVD_ERR_INVALID, "bad count or null");
+    HIPCHK(launch_philox_words(in, out, count, (hipStream_t)stream));
+    return RSVD_OK;
+}
+
+int64_t rsvd_plan_workspace_bytes(const rsvd_plan_t* plan) { return plan ? (int64_t)plan->ws_bytes : 0; }
+
+void rsvd_plan_destroy(rsvd_plan_t* plan) { plan_free(plan); }
+
+const char* rsvd_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+"""Python API over librsvd.  PyTorch provides device memory and streams only;
+every step of the factorisation runs in the library's HIP kernels.
+
+Alg. RSVD and Alg. TSVD refer to Sec. II.B and Sec. II.A of Kohn et al.,
+"Probabilistic low-rank factorization accelerates tensor network simulations
+of critical quantum many-body ground states".
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float64: L.RSVD_F64, torch.float32: L.RSVD_F32}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_matrix(A):
+    if not isinstance(A, torch.Tensor) or A.dim() != 2:
+        raise ValueError("A must be a 2-D torch tensor")
+    if A.device.type != "cuda":
+        raise ValueError("A must be on a GPU device")
+    if A.dtype not in _DT:
+        raise ValueError("A must be float64 or float32")
+    if A.stride(1) != 1:
+        A = A.contiguous()
+    return A
+
+
+def _outputs(m, n, k, dtype, device):
+    kk = min(k, m, n)
+    U = torch.empty((m, kk), dtype=dtype, device=device)
+    S = torch.empty((kk,), dtype=dtype, device=device)
+    VT = torch.empty((kk, n), dtype=dtype, device=device)
+    return U, S, VT
+
+
+def rsvd_truncate(A, k, p=10, q=2, seed=0, delta=0.0, prec="f64"):
+    """Rank-k randomized truncated SVD (Alg. RSVD).  Returns (U, S, VT, w, k_kept)
+    with w the discarded squared Frobenius weight (FP64 tensor of shape [1]) and
+    k_kept an int64 tensor of shape [1]; U/S/VT beyond k_kept are zero."""
+    A = _check_matrix(A)
+    m, n = A.shape
+    U, S, VT = _outputs(m, n, k, A.dtype, A.device)
+    w = torch.empty(1, dtype=torch.float64, device=A.device)
+    kk = torch.empty(1, dtype=torch.int64, device=A.device)
+    L.check(L.lib().rsvd_truncate(A.data_ptr(), _DT[A.dtype], m, n, A.stride(0), k, p, q,
+                                  ctypes.c_uint64(seed), float(delta), L.PREC[prec], U.data_ptr(),
+                                  U.shape[1], S.data_ptr(), VT.data_ptr(), n, w.data_ptr(),
+                                  kk.data_ptr(), _stream()))
+    return U, S, VT, w, kk
+
+
+def fullsvd_truncate(A, k, delta=0.0):
+    """Truncation by the full SVD (Alg. TSVD), block one-sided Jacobi in FP64."""
+    A = _check_matrix(A)
+    m, n = A.shape
+    U, S, VT = _outputs(m, n, k, A.dtype, A.device)
+    w = torch.empty(1, dtype=torch.float64, device=A.device)
+    kk = torch.empty(1, dtype=torch.int64, device=A.device)
+    L.check(L.lib().fullsvd_truncate(A.data_ptr(), _DT[A.dtype], m, n, A.stride(0), k, float(delta),
+                                     U.data_ptr(), U.shape[1], S.data_ptr(), VT.data_ptr(), n,
+                                     w.data_ptr(), kk.data_ptr(), _stream()))
+    return U, S, VT, w, kk
+
+
+def gaussian(seed, n, l, device="cuda"):
+    """The n x l Gaussian test matrix (FP64) the RSVD draws for this seed."""
+    out = torch.empty((n, l), dtype=torch.float64, device=device)
+    L.check(L.lib().rsvd_gaussian(ctypes.c_uint64(seed), n, l, out.data_ptr(), _stream()))
+    return out
+
+
+def philox4x32_10(words):
+    """Device Philox4x32-10: words is a (count x 6) array of uint32 counter and
+    key words; returns the (count x 4) output words as a numpy uint32 array."""
+    import numpy as np
+    w = np.ascontiguousarray(np.asarray(words, dtype=np.uint32)).view(np.int32)
+    inp = torch.from_numpy(w).cuda()
+    out = torch.empty((inp.shape[0], 4), dtype=torch.int32, device=inp.device)
+    L.check(L.lib().rsvd_philox4x32_10(inp.data_ptr(), out.data_ptr(), inp.shape[0], _stream()))
+    torch.cuda.current_stream().synchronize()
+    return out.cpu().numpy().view(np.uint32)
+
+
+class Plan:
+    """A batch of independent truncations of arbitrary sizes run together.
+
+    problems: list of dicts with keys m, n, k and (RSVD) p, q, seed, and
+    optionally delta.  Outputs are allocated once by the plan and reused by
+    every execute, so repeated executes on the same inputs upload nothing.
+    """
+
+    def __init__(self, problems, dtype=torch.float64, prec="f64", fullsvd=False, graph=True,
+                 save=False, device="cuda"):
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.fullsvd = fullsvd
+        self.problems = [dict(pr) for pr in problems]
+        n = len(self.problems)
+        arr = (L.RsvdProblem * n)()
+        for i, pr in enumerate(self.problems):
+            arr[i].m = pr["m"]
+            arr[i].n = pr["n"]
+            arr[i].lda = pr.get("lda", pr["n"])
+            arr[i].k = pr["k"]
+            arr[i].p = pr.get("p", 0)
+            arr[i].q = pr.get("q", 0)
+            arr[i].seed = pr.get("seed", 0)
+            arr[i].delta_trunc = pr.get("delta", 0.0)
+            arr[i].ldu = 0
+            arr[i].ldvt = 0
+        flags = (L.PLAN_FULLSVD if fullsvd else 0) | (L.PLAN_GRAPH if graph else 0) | \
+                (L.PLAN_SAVE if save else 0)
+        h = ctypes.c_void_p()
+        L.check(L.lib().rsvd_plan_create(arr, n, _DT[dtype], L.PREC[prec], flags, ctypes.byref(h)))
+        self._h = h
+        self.outputs = [_outputs(pr["m"], pr["n"], pr["k"], dtype, self.device) for pr in self.problems]
+        self.w = torch.empty(n, dtype=torch.float64, device=self.device)
+        self.k_kept = torch.empty(n, dtype=torch.int64, device=self.device)
+        self.info = torch.empty(n, dtype=torch.int32, device=self.device)
+        self._ptrs = (L.ptr_array([o[0].data_ptr() for o in self.outputs]),
+                      L.ptr_array([o[1].data_ptr() for o in self.outputs]),
+                      L.ptr_array([o[2].data_ptr() for o in self.outputs]))
+        self._keep = None
+
+    @property
+    def workspace_bytes(self):
+        return int(L.lib().rsvd_plan_workspace_bytes(self._h))
+
+    def execute(self, As):
+        """Runs every problem on the current stream; As: list of device tensors.
+        Returns (outputs, w, k_kept, info) without synchronising."""
+        if len(As) != len(self.problems):
+            raise ValueError("one input matrix per problem")
+        for A, pr in zip(As, self.problems):
+            if A.shape != (pr["m"], pr["n"]) or A.dtype != self.dtype or A.device.type != "cuda":
+                raise ValueError("input matrix does not match its problem")
+            if A.stride(1) != 1 or A.stride(0) != pr.get("lda", pr["n"]):
+                raise ValueError("input matrix must be row-major with the plan's lda")
+        aptr = L.ptr_array([A.data_ptr() for A in As])
+        self._keep = As
+        L.check(L.lib().rsvd_plan_execute(self._h, aptr, self._ptrs[0], self._ptrs[1], self._ptrs[2],
+                                          self.w.data_ptr(), self.k_kept.data_ptr(),
+                                          self.info.data_ptr(), _stream()))
+        return self.outputs, self.w, self.k_kept, self.info
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().rsvd_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
