@@ -1,0 +1,174 @@
+"""Benchmark: rank-k RSVDs per second on one MI355X.
+
+Workload (default): the TEBD-shaped critical-spectrum batch, 32 matrices
+512 x 512 with s_i = i^-1.5 and Haar factors, k = 256, p = 16, q = 2, solved
+as one batched plan (one HIP-graph launch per step).  Inputs are resident in
+HBM before timing starts.  A step is one RSVD of every matrix of the batch.
+
+Also reported: the same-GPU full-SVD truncation (block one-sided Jacobi) on
+the same batch, the plain FP64 one-at-a-time RSVD, the accuracy of both at
+equal truncation error, and the CPU FP64 oracle on a bounded sample.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f64|f32|bf16]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the full-SVD and one-at-a-time legs")
+    ap.add_argument("--cpu-sample", type=int, default=16)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(mats, probs, sample):
+    """The FP64 oracle (untuned), one problem per thread, on a bounded sample."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    threads = max(1, min(cores, 16, sample))
+    idx = list(range(min(sample, len(mats))))
+    oracle.lib()
+
+    def one(i):
+        pr = probs[i]
+        return oracle.rsvd(mats[i], pr.k, pr.p, pr.q, pr.seed).status
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        st = list(ex.map(one, idx))
+    dt = time.perf_counter() - t0
+    assert all(s == 0 for s in st)
+    return {"value": len(idx) / dt, "unit": "RSVDs/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(idx)} of the {len(mats)} matrices (512x512, k=256 p=16 q=2), "
+                      f"FP64 C oracle, one matrix per thread, {dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is "
+                                   "design-only (independent problems would be split by flop count)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1710_01463_amd as P
+    import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    W = wl.c2(args.batch)
+    probs = W.problems
+    log(f"[bench] generating {len(probs)} matrices {probs[0].m}x{probs[0].n}")
+    mats = [pr.matrix() for pr in probs]
+    dtype = torch.float64 if args.prec == "f64" else torch.float32
+    As = [torch.from_numpy(A).to(dtype).cuda() for A in mats]
+    plist = [dict(m=pr.m, n=pr.n, k=pr.k, p=pr.p, q=pr.q, seed=pr.seed) for pr in probs]
+    plan = P.Plan(plist, dtype, args.prec, graph=True)
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        plan.execute(As)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.execute(As)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / args.steps * 1e3
+    value = len(probs) / (ms / 1e3)
+    gemm_flops = sum(pr.gemm_flops() for pr in probs)
+    outs, w, kk, info = plan.execute(As)
+    torch.cuda.synchronize()
+    info = info.cpu().numpy()
+    w_rsvd = w.cpu().numpy()
+    assert np.all(info == 0), f"non-zero status {info}"
+
+    result = {
+        "metric": "rank-k RSVDs/sec (batched, one graph launch per step)",
+        "value": value,
+        "unit": "RSVDs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32+f64", "bf16": "bf16+f64"}[args.prec],
+        "data": "synthetic: A = U diag(i^-1.5) V^T, Haar U, V (seeded)",
+        "config": {"workload": f"C2: {len(probs)} x 512x512, s_i=i^-1.5, k=256 p=16 q=2, "
+                               f"sketch/power arithmetic {args.prec}",
+                   "batch": len(probs), "m": 512, "n": 512, "k": 256, "p": 16, "q": 2},
+        "gemm_tflops": gemm_flops / (ms / 1e3) / 1e12,
+    }
+
+    if not args.no_compare:
+        # same-GPU full-SVD truncation on the same batch (FP64 Jacobi)
+        log("[bench] full-SVD leg")
+        fplan = P.Plan([dict(m=pr.m, n=pr.n, k=pr.k) for pr in probs], dtype, "f64", fullsvd=True)
+        fplan.execute(As)
+        torch.cuda.synchronize()
+        fsteps = max(1, min(3, args.steps))
+        t0 = time.perf_counter()
+        for _ in range(fsteps):
+            fplan.execute(As)
+        torch.cuda.synchronize()
+        fms = (time.perf_counter() - t0) / fsteps * 1e3
+        _, fw, fkk, finfo = fplan.execute(As)
+        torch.cuda.synchronize()
+        fw = fw.cpu().numpy()
+        # plain FP64 RSVD, one problem per call
+        log("[bench] one-at-a-time leg")
+        A64 = [torch.from_numpy(A).cuda() for A in mats]
+        pr = probs[0]
+        P.rsvd_truncate(A64[0], pr.k, pr.p, pr.q, pr.seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for A, pr in zip(A64, probs):
+            P.rsvd_truncate(A, pr.k, pr.p, pr.q, pr.seed)
+        torch.cuda.synchronize()
+        oms = (time.perf_counter() - t0) * 1e3
+        # equal truncation error: eps_F / delta_EY from the exact discarded weights
+        eps_ratio = float(np.mean(np.sqrt(w_rsvd / fw)))
+        result["compare"] = {
+            "fullsvd_per_s": len(probs) / (fms / 1e3),
+            "fullsvd_ms_per_step": fms,
+            "speedup_vs_fullsvd": fms / ms,
+            "one_at_a_time_f64_per_s": len(probs) / (oms / 1e3),
+            "speedup_vs_one_at_a_time_f64": oms / ms,
+            "eps_F_over_delta_EY_rsvd": eps_ratio,
+            "eps_F_over_delta_EY_fullsvd": 1.0,
+        }
+
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle leg")
+        result["cpu_baseline"] = cpu_baseline(mats, probs, args.cpu_sample)
+
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

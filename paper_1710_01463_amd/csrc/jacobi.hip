@@ -19,58 +19,102 @@
 namespace rsvd {
 
 constexpr int JR = 2 * JAC_B;  // rows per block pair
-constexpr int JCH = 64;        // column chunk
-constexpr int JAC_MAX_INNER = 12;
+constexpr int JCH = 128;       // column chunk staged through LDS
+constexpr int JPF = JR * JCH / 256;  // prefetched doubles per thread
 
 __device__ __forceinline__ int rr_block(int pos, int round, int nb)
 {
     return pos == 0 ? 0 : ((pos - 1 + round) % (nb - 1)) + 1;
 }
 
-// out rows (32) = Ps (32 x 32) * rows of M (32 x ncols), in place on M.
+// Rotation (c, s) that zeroes the (p, q) entry of a symmetric 2 x 2 block
+// [a g; g b] under x_p <- c x_p - s x_q, x_q <- s x_p + c x_q (the classical
+// Hestenes/Jacobi formula).  Identity when |g| <= tol sqrt(a b).
+__device__ __forceinline__ void jac_rotation(double a, double b, double g, double tol, double& cs, double& sn)
+{
+    cs = 1.0;
+    sn = 0.0;
+    if (a > 0.0 && b > 0.0 && g * g > tol * tol * a * b) {
+        const double zeta = (b - a) / (2.0 * g);
+        double t;
+        if (fabs(zeta) > 1e150)
+            t = 0.5 / zeta;
+        else
+            t = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        cs = rsqrt(1.0 + t * t);
+        sn = cs * t;
+    }
+}
+
+// Loads the 32 x JCH chunk (rows via rowmap, columns c0..) of M into registers.
+__device__ __forceinline__ void load_chunk(double (&pre)[JPF], const double* __restrict__ M, int64_t ldm,
+                                           int ncols, int c0, const int* rowmap)
+{
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < JPF; ++i) {
+        const int e = tid + 256 * i;
+        const int a = e / JCH, cc = e % JCH;
+        const int gr = rowmap[a], gc = c0 + cc;
+        pre[i] = (gr >= 0 && gc < ncols) ? M[(int64_t)gr * ldm + gc] : 0.0;
+    }
+}
+__device__ __forceinline__ void store_chunk(const double (&pre)[JPF], double (*Xs)[JCH + 1])
+{
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < JPF; ++i) {
+        const int e = tid + 256 * i;
+        Xs[e / JCH][e % JCH] = pre[i];
+    }
+}
+
+// rows of M (32 of them, via rowmap) <- Ps (32 x 32) * rows of M, in place;
+// the next chunk is prefetched into registers while the current one is used.
 __device__ void apply_rotation(double* __restrict__ M, int64_t ldm, int ncols, const int* rowmap,
                                double (*Ps)[JR + 1], double (*Xs)[JCH + 1])
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
-    const int ti = wave & 1;
+    double pre[JPF];
+    load_chunk(pre, M, ldm, ncols, 0, rowmap);
     for (int c0 = 0; c0 < ncols; c0 += JCH) {
-        for (int e = tid; e < JR * JCH; e += 256) {
-            const int a = e / JCH, cc = e % JCH;
-            const int gr = rowmap[a], gc = c0 + cc;
-            Xs[a][cc] = (gr >= 0 && gc < ncols) ? M[(int64_t)gr * ldm + gc] : 0.0;
-        }
+        store_chunk(pre, Xs);
         __syncthreads();
+        if (c0 + JCH < ncols) load_chunk(pre, M, ldm, ncols, c0 + JCH, rowmap);
+        // 2 row tiles x (JCH / 16) column tiles; wave w takes column tiles w, w + 4, ...
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int tj = (wave >> 1) * 2 + h;
-            dbl4 acc = {0, 0, 0, 0};
+        for (int tj = wave; tj < JCH / 16; tj += 4) {
+            dbl4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 #pragma unroll
             for (int kk = 0; kk < JR; kk += 4) {
-                const double av = Ps[ti * 16 + l16][kk + lq];
                 const double bv = Xs[kk + lq][tj * 16 + l16];
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ps[l16][kk + lq], bv, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ps[16 + l16][kk + lq], bv, acc1, 0, 0, 0);
             }
+            const int gc = c0 + tj * 16 + l16;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = ti * 16 + lq + 4 * r;
-                const int gr = rowmap[i], gc = c0 + tj * 16 + l16;
-                if (gr >= 0 && gc < ncols) M[(int64_t)gr * ldm + gc] = acc[r];
+                const int g0 = rowmap[lq + 4 * r], g1 = rowmap[16 + lq + 4 * r];
+                if (gc < ncols) {
+                    if (g0 >= 0) M[(int64_t)g0 * ldm + gc] = acc0[r];
+                    if (g1 >= 0) M[(int64_t)g1 * ldm + gc] = acc1[r];
+                }
             }
         }
         __syncthreads();
     }
 }
 
+constexpr int JAC_INNER_SWEEPS = 1;
+
 __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc* __restrict__ descs,
                                                            const int* __restrict__ pair_begin, int nprob,
                                                            int sweep, int round)
 {
     __shared__ double Xs[JR][JCH + 1];
-    __shared__ double Hs[JR][JR + 1];
+    __shared__ double Hbuf[2][JR][JR + 1];
     __shared__ double Ps[JR][JR + 1];
-    __shared__ double cs_s[JR / 2], sn_s[JR / 2];
-    __shared__ int pp_s[JR / 2], qq_s[JR / 2];
     __shared__ int rowmap[JR];
     __shared__ int any_rot;
 
@@ -101,14 +145,13 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc* __rest
     {
         const int wi = wave >> 1, wj = wave & 1;
         dbl4 acc = {0, 0, 0, 0};
+        double pre[JPF];
+        load_chunk(pre, X, ldx, C, 0, rowmap);
         for (int c0 = 0; c0 < C; c0 += JCH) {
-            for (int e = tid; e < JR * JCH; e += 256) {
-                const int a = e / JCH, cc = e % JCH;
-                const int gr = rowmap[a], gc = c0 + cc;
-                Xs[a][cc] = (gr >= 0 && gc < C) ? X[(int64_t)gr * ldx + gc] : 0.0;
-            }
+            store_chunk(pre, Xs);
             __syncthreads();
-#pragma unroll
+            if (c0 + JCH < C) load_chunk(pre, X, ldx, C, c0 + JCH, rowmap);
+#pragma unroll 8
             for (int kk = 0; kk < JCH; kk += 4) {
                 const double av = Xs[wi * 16 + l16][kk + lq];
                 const double bv = Xs[wj * 16 + l16][kk + lq];
@@ -117,84 +160,61 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc* __rest
             __syncthreads();
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Hs[wi * 16 + lq + 4 * r][wj * 16 + l16] = acc[r];
+        for (int r = 0; r < 4; ++r) Hbuf[0][wi * 16 + lq + 4 * r][wj * 16 + l16] = acc[r];
     }
     __syncthreads();
     // symmetrise from the upper triangle, identity for P
     for (int e = tid; e < JR * JR; e += 256) {
         const int i = e / JR, j = e % JR;
-        if (i > j) Hs[i][j] = Hs[j][i];
+        if (i > j) Hbuf[0][i][j] = Hbuf[0][j][i];
         Ps[i][j] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
     for (int e = tid; e < JR * JR; e += 256) {
         const int i = e / JR, j = e % JR;
         if (i < j) {
-            const double a = Hs[i][i], c = Hs[j][j], g = Hs[i][j];
-            if (a > 0.0 && c > 0.0 && fabs(g) > tol * sqrt(a) * sqrt(c)) any_rot = 1;
+            const double a = Hbuf[0][i][i], c = Hbuf[0][j][j], g = Hbuf[0][i][j];
+            if (a > 0.0 && c > 0.0 && g * g > tol * tol * a * c) any_rot = 1;
         }
     }
     __syncthreads();
     if (!any_rot) return;
     if (tid == 0) d.rot[sweep] = 1;
 
-    // ---- inner cyclic Jacobi on the 32 x 32 Gram matrix (parallel order)
-    for (int isw = 0; isw < JAC_MAX_INNER; ++isw) {
-        __syncthreads();
-        if (tid == 0) any_rot = 0;
-        __syncthreads();
+    // ---- inner cyclic Jacobi on the 32 x 32 Gram matrix, parallel order.
+    // Thread (pi_, pj_) owns the 2 x 2 block (pair pi_ rows) x (pair pj_ cols)
+    // of H and the 2 x 2 block (pair pi_ rows) x (columns 2 pj_, 2 pj_ + 1) of
+    // P.  H is double-buffered so one barrier per step suffices.
+    const int pr_i = tid >> 4, pr_j = tid & 15;
+    int cur = 0;
+    for (int isw = 0; isw < JAC_INNER_SWEEPS; ++isw) {
         for (int step = 0; step < JR - 1; ++step) {
-            if (tid < JR / 2) {
-                const int p = rr_block(tid, step, JR);
-                const int q = rr_block(JR - 1 - tid, step, JR);
-                const double a = Hs[p][p], c = Hs[q][q], g = Hs[p][q];
-                double cs = 1.0, sn = 0.0;
-                if (a > 0.0 && c > 0.0 && fabs(g) > tol * sqrt(a) * sqrt(c)) {
-                    const double zeta = (c - a) / (2.0 * g);
-                    double tt;
-                    if (fabs(zeta) > 1e150)
-                        tt = 0.5 / zeta;
-                    else
-                        tt = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    cs = 1.0 / sqrt(1.0 + tt * tt);
-                    sn = cs * tt;
-                    any_rot = 1;
-                }
-                cs_s[tid] = cs;
-                sn_s[tid] = sn;
-                pp_s[tid] = p;
-                qq_s[tid] = q;
+            const int p_i = rr_block(pr_i, step, JR), q_i = rr_block(JR - 1 - pr_i, step, JR);
+            const int p_j = rr_block(pr_j, step, JR), q_j = rr_block(JR - 1 - pr_j, step, JR);
+            double (*H)[JR + 1] = Hbuf[cur];
+            double (*Hn)[JR + 1] = Hbuf[cur ^ 1];
+            double ci, si, cj, sj;
+            jac_rotation(H[p_i][p_i], H[q_i][q_i], H[p_i][q_i], tol, ci, si);
+            jac_rotation(H[p_j][p_j], H[q_j][q_j], H[p_j][q_j], tol, cj, sj);
+            const double b00 = H[p_i][p_j], b01 = H[p_i][q_j], b10 = H[q_i][p_j], b11 = H[q_i][q_j];
+            const double t00 = ci * b00 - si * b10, t01 = ci * b01 - si * b11;
+            const double t10 = si * b00 + ci * b10, t11 = si * b01 + ci * b11;
+            Hn[p_i][p_j] = t00 * cj - t01 * sj;
+            Hn[p_i][q_j] = t00 * sj + t01 * cj;
+            Hn[q_i][p_j] = t10 * cj - t11 * sj;
+            Hn[q_i][q_j] = t10 * sj + t11 * cj;
+            if (si != 0.0) {
+                const int c0 = 2 * pr_j, c1 = 2 * pr_j + 1;
+                const double x0 = Ps[p_i][c0], x1 = Ps[p_i][c1], y0 = Ps[q_i][c0], y1 = Ps[q_i][c1];
+                Ps[p_i][c0] = ci * x0 - si * y0;
+                Ps[p_i][c1] = ci * x1 - si * y1;
+                Ps[q_i][c0] = si * x0 + ci * y0;
+                Ps[q_i][c1] = si * x1 + ci * y1;
             }
-            __syncthreads();
-            for (int e = tid; e < (JR / 2) * JR; e += 256) {
-                const int pr = e / JR, c = e % JR;
-                const double cs = cs_s[pr], sn = sn_s[pr];
-                if (sn != 0.0) {
-                    const int p = pp_s[pr], q = qq_s[pr];
-                    const double hp = Hs[p][c], hq = Hs[q][c];
-                    Hs[p][c] = cs * hp - sn * hq;
-                    Hs[q][c] = sn * hp + cs * hq;
-                    const double xp = Ps[p][c], xq = Ps[q][c];
-                    Ps[p][c] = cs * xp - sn * xq;
-                    Ps[q][c] = sn * xp + cs * xq;
-                }
-            }
-            __syncthreads();
-            for (int e = tid; e < (JR / 2) * JR; e += 256) {
-                const int pr = e / JR, r = e % JR;
-                const double cs = cs_s[pr], sn = sn_s[pr];
-                if (sn != 0.0) {
-                    const int p = pp_s[pr], q = qq_s[pr];
-                    const double hp = Hs[r][p], hq = Hs[r][q];
-                    Hs[r][p] = cs * hp - sn * hq;
-                    Hs[r][q] = sn * hp + cs * hq;
-                }
-            }
+            cur ^= 1;
             __syncthreads();
         }
-        if (!any_rot) break;
     }
-    __syncthreads();
 
     // ---- apply the accumulated rotation to the rows of X and of P
     apply_rotation(X, ldx, C, rowmap, Ps, Xs);

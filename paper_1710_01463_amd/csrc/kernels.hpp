@@ -50,20 +50,23 @@ struct QrDesc {
     double* Qout;      // rows x l, ld = l
     double* G;         // l x l Gram
     double* L;         // l x l Cholesky factor (lower)
+    double* D;         // ceil(l/16) inverses of the 16 x 16 diagonal blocks of L
     int* flag;         // breakdown flag: set to 1 when Cholesky QR cannot be used
     int rows, l;
     int min_elem;      // Elem of Min
     int pad_;
 };
 
-// Cholesky of G into L; sets *flag on breakdown.  max_l: largest l of the batch.
+// Cholesky of G into L and the diagonal-block inverses D; sets *flag on
+// breakdown.  max_l: largest l of the batch.  Skips problems with Qout ==
+// nullptr or *flag already set.
 constexpr int CHOL_MAX_L = 1024;
 hipError_t launch_chol(const QrDesc* d, int nprob, int max_l, hipStream_t s);
-// Qout = src * L^-T where src = Min (from_min = 1) or Qout itself (from_min = 0, in place).
-// row_begin: prefix sums of ceil(rows / 16) per problem.
+// Qout = src L^-T, src = Min (from_min = 1) or Qout (from_min = 0, in place);
+// row_begin: prefix sums of ceil(rows / 16).
 hipError_t launch_trsm(const QrDesc* d, const int* row_begin, int nprob, int total_blocks, int from_min,
                        int max_l, hipStream_t s);
-// Raises the dynamic-LDS limit of the Cholesky and substitution kernels.
+// Raises the dynamic-LDS limit of the Cholesky kernel.
 hipError_t init_qr_kernels();
 // Householder QR of Min into Qout for the problems whose flag is set.
 hipError_t launch_householder(const QrDesc* d, int nprob, hipStream_t s);

@@ -34,7 +34,11 @@ int fail(int code, const std::string& msg)
         if (e_ != hipSuccess) return fail(RSVD_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-constexpr int JAC_MAX_SWEEPS = 30;
+// Sweep caps of the block Jacobi: the small SVD of B typically converges in 7-9
+// sweeps, the full SVD in more; every sweep past convergence costs only empty
+// launches, but they add up.
+constexpr int JAC_MAX_SWEEPS_RSVD = 20;
+constexpr int JAC_MAX_SWEEPS_FULL = 30;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -64,7 +68,8 @@ struct ProbHost {
     // workspace offsets (bytes)
     size_t o_acast, o_om, o_m[2], o_q[2], o_g, o_l1, o_l2, o_b, o_p, o_sig, o_perm, o_norm, o_part,
         o_flags, o_rot, o_info_local;
-    std::vector<size_t> o_mstage, o_qstage, o_l1stage, o_l2stage;
+    std::vector<size_t> o_mstage, o_qstage, o_l1stage, o_l2stage;  // l1/l2: inverse Cholesky factors
+    size_t o_lwork, o_dwork;
     int nchunks;
 };
 
@@ -89,6 +94,7 @@ struct rsvd_plan {
     bool fullsvd = false;
     std::vector<ProbHost> probs;
     int max_l = 0, max_nb = 2, max_q = 0;
+    int max_sweeps = 20;
     Elem e_store = E_F64, e_sketch = E_F64, e_y = E_F64;
     bool need_cast = false;
     size_t ws_bytes = 0;
@@ -179,6 +185,8 @@ void layout(rsvd_plan& P)
         h.o_l1stage.assign(nst, 0);
         h.o_l2stage.assign(nst, 0);
         size_t shared_m[2], shared_q[2], sl1 = 0, sl2 = 0;
+        h.o_lwork = take(sizeof(double) * l * l);
+        h.o_dwork = take(sizeof(double) * ((l + 15) / 16) * 256);
         if (!save) {
             shared_m[0] = take((size_t)elem_bytes(P.e_y) * m * l);
             shared_m[1] = take((size_t)elem_bytes(P.e_y) * n * l);
@@ -204,9 +212,9 @@ void layout(rsvd_plan& P)
         h.o_g = take(sizeof(double) * l * l);
         h.o_b = take(sizeof(double) * (size_t)h.R * h.C);
     }
-    // flags: per problem (2 q_max + 1) QR flags followed by JAC_MAX_SWEEPS rot flags
+    // flags: per problem (2 q_max + 1) QR flags followed by max_sweeps rot flags
     P.off_flags_base = take(0);
-    const int per = (int)(2 * P.max_q + 1) + JAC_MAX_SWEEPS;
+    const int per = (int)(2 * P.max_q + 1) + P.max_sweeps;
     for (size_t b = 0; b < P.probs.size(); ++b) {
         P.probs[b].o_flags = P.off_flags_base + sizeof(int) * (size_t)per * b;
         P.probs[b].o_rot = P.probs[b].o_flags + sizeof(int) * (size_t)(2 * P.max_q + 1);
@@ -335,28 +343,27 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
         P.trsm.clear();
         for (int s = 0; s < nst; ++s) {
             std::vector<GemmDesc> dsk(np), dg1(np), dg2(np);
-            std::vector<QrDesc> dq(np);
-            std::vector<int> rowblk(np);
+            std::vector<QrDesc> dq(np), dq2(np);
+            std::vector<int> rowblk(np, 0), rowblk2(np, 0);
+            const GemmDesc none = gd(nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0, 0, 0, one);
             for (int b = 0; b < np; ++b) {
                 const ProbHost& h = P.probs[b];
                 const int l = h.l;
                 const bool active = s <= 2 * h.q;
+                const bool final_stage = s == 2 * h.q;
                 const int64_t rows = (s % 2 == 0) ? h.m : h.n;
+                memset(&dq[b], 0, sizeof(QrDesc));
+                dq[b].flag = const_cast<int*>(one);
+                dq[b].l = l;
+                dq2[b] = dq[b];
+                dsk[b] = dg1[b] = dg2[b] = none;
+                if (!active) continue;
                 const void* Aop = P.need_cast ? (const void*)wsp<char>(P, h.o_acast) : A[b];
                 const int64_t lda_op = P.need_cast ? h.n : h.lda;
-                void* M = active ? (void*)wsp<char>(P, h.o_mstage[s]) : nullptr;
-                double* Qs = active ? wsp<double>(P, h.o_qstage[s]) : nullptr;
+                void* M = wsp<char>(P, h.o_mstage[s]);
+                double* Qs = wsp<double>(P, h.o_qstage[s]);
                 int* flag = wsp<int>(P, h.o_flags) + s;
-                if (!active) {
-                    dsk[b] = gd(nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0, 0, 0, one);
-                    dg1[b] = dsk[b];
-                    dg2[b] = dsk[b];
-                    memset(&dq[b], 0, sizeof(QrDesc));
-                    dq[b].flag = const_cast<int*>(one);
-                    dq[b].l = l;
-                    rowblk[b] = 0;
-                    continue;
-                }
+                double* G = wsp<double>(P, h.o_g);
                 if (s == 0) {
                     dsk[b] = gd(Aop, lda_op, 0, wsp<char>(P, h.o_om), l, 0, M, l, (int)h.m, l, (int)h.n);
                 } else if (s % 2 == 1) {
@@ -366,20 +373,24 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
                     dsk[b] = gd(Aop, lda_op, 0, wsp<double>(P, h.o_qstage[s - 1]), l, 0, M, l, (int)h.m, l,
                                 (int)h.n);
                 }
-                double* G = wsp<double>(P, h.o_g);
+                // pass 1: G = M^T M, L L^T = G, Q = M L^-T
                 dg1[b] = gd(M, l, 1, M, l, 0, G, l, l, l, (int)rows, flag);
-                dg2[b] = gd(Qs, l, 1, Qs, l, 0, G, l, l, l, (int)rows, flag);
                 QrDesc& q = dq[b];
-                memset(&q, 0, sizeof(q));
                 q.Min = M;
                 q.Qout = Qs;
                 q.G = G;
-                q.L = wsp<double>(P, h.o_l1stage[s]);
+                q.L = wsp<double>(P, h.o_lwork);
+                q.D = wsp<double>(P, h.o_dwork);
                 q.flag = flag;
                 q.rows = (int)rows;
-                q.l = l;
                 q.min_elem = P.e_y;
                 rowblk[b] = (int)((rows + 15) / 16);
+                // pass 2 (final basis only), in place: G = Q^T Q, Q = Q L2^-T
+                if (final_stage) {
+                    dg2[b] = gd(Qs, l, 1, Qs, l, 0, G, l, l, l, (int)rows, flag);
+                    dq2[b] = q;
+                    rowblk2[b] = rowblk[b];
+                }
             }
             // X operand element of the sketch GEMMs: Omega at s = 0, FP64 bases afterwards
             P.g_sketch.push_back(add_gemm(B, gk, ea_sk, s == 0 ? P.e_sketch : E_F64, P.e_y, dsk));
@@ -387,13 +398,9 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             P.g_gram2.push_back(add_gemm(B, GK_F64, E_F64, E_F64, E_F64, dg2));
             std::vector<int> ones(np, 1);
             P.qr.push_back(add_idx(B, dq, ones));
-            // second Cholesky pass writes L2: separate descriptor copy
-            std::vector<QrDesc> dq2 = dq;
-            for (int b = 0; b < np; ++b)
-                if (s <= 2 * P.probs[b].q) dq2[b].L = wsp<double>(P, P.probs[b].o_l2stage[s]);
             P.qr.push_back(add_idx(B, dq2, ones));
             P.trsm.push_back(add_idx(B, dq, rowblk));
-            P.trsm.push_back(add_idx(B, dq2, rowblk));
+            P.trsm.push_back(add_idx(B, dq2, rowblk2));
         }
         // B = Q^T A in FP64 from the stored A
         {
@@ -484,7 +491,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             f.n = (int)h.n;
             f.k = (int)h.k;
             f.mode = h.mode;
-            f.max_sweeps = JAC_MAX_SWEEPS;
+            f.max_sweeps = P.max_sweeps;
             f.delta = h.delta;
             cols[b] = (int)h.k;
         }
@@ -536,18 +543,21 @@ int enqueue(rsvd_plan& P, hipStream_t s)
         for (int st = 0; st < nst; ++st) {
             int rc;
             if ((rc = gemm(P, P.g_sketch[st], s)) != RSVD_OK) return rc;
-            // Cholesky QR pass 1
-            if ((rc = gemm(P, P.g_gram1[st], s)) != RSVD_OK) return rc;
             const IdxLaunch& q1 = P.qr[2 * st];
             const IdxLaunch& q2 = P.qr[2 * st + 1];
             const IdxLaunch& t1 = P.trsm[2 * st];
             const IdxLaunch& t2 = P.trsm[2 * st + 1];
+            // Cholesky QR pass 1
+            if ((rc = gemm(P, P.g_gram1[st], s)) != RSVD_OK) return rc;
             LCHK(launch_chol(dp<QrDesc>(P, q1.off_desc), np, P.max_l, s));
             LCHK(launch_trsm(dp<QrDesc>(P, t1.off_desc), dp<int>(P, t1.off_begin), np, t1.total, 1, P.max_l, s));
-            // pass 2 on the result of pass 1
-            if ((rc = gemm(P, P.g_gram2[st], s)) != RSVD_OK) return rc;
-            LCHK(launch_chol(dp<QrDesc>(P, q2.off_desc), np, P.max_l, s));
-            LCHK(launch_trsm(dp<QrDesc>(P, t2.off_desc), dp<int>(P, t2.off_begin), np, t2.total, 0, P.max_l, s));
+            // pass 2 for the problems whose final basis this is
+            if (t2.total > 0) {
+                if ((rc = gemm(P, P.g_gram2[st], s)) != RSVD_OK) return rc;
+                LCHK(launch_chol(dp<QrDesc>(P, q2.off_desc), np, P.max_l, s));
+                LCHK(launch_trsm(dp<QrDesc>(P, t2.off_desc), dp<int>(P, t2.off_begin), np, t2.total, 0, P.max_l,
+                                 s));
+            }
             // Householder for the problems whose Cholesky QR broke down
             LCHK(launch_householder(dp<QrDesc>(P, q1.off_desc), np, s));
         }
@@ -557,7 +567,7 @@ int enqueue(rsvd_plan& P, hipStream_t s)
         LCHK(launch_copy_f64(dp<CopyDesc>(P, P.copy.off_desc), dp<int>(P, P.copy.off_begin), np, P.copy.total, s));
     }
     LCHK(launch_eye(dp<EyeDesc>(P, P.eye.off_desc), dp<int>(P, P.eye.off_begin), np, P.eye.total, s));
-    for (int sw = 0; sw < JAC_MAX_SWEEPS; ++sw)
+    for (int sw = 0; sw < P.max_sweeps; ++sw)
         for (int r = 0; r < P.max_nb - 1; ++r)
             LCHK(launch_jacobi_round(dp<JacDesc>(P, P.jac.off_desc), dp<int>(P, P.jac.off_begin), np, P.jac.total,
                                      sw, r, s));
@@ -611,6 +621,7 @@ int plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsv
     P->prec = fullsvd ? RSVD_PREC_F64 : prec;
     P->flags = flags;
     P->fullsvd = fullsvd;
+    P->max_sweeps = fullsvd ? JAC_MAX_SWEEPS_FULL : JAC_MAX_SWEEPS_RSVD;
     P->e_store = store_elem(dt);
     P->e_sketch = P->prec == RSVD_PREC_F64 ? E_F64 : (P->prec == RSVD_PREC_F32 ? E_F32 : E_BF16);
     P->e_y = P->prec == RSVD_PREC_F64 ? E_F64 : E_F32;

@@ -2,12 +2,15 @@
 // and the re-orthonormalisation after every product of the power iteration).
 //
 // Cholesky QR: with the Gram matrix G = M^T M computed in FP64 by the batched
-// GEMM, factor G = L L^T and form Q = M L^-T.  Two passes (CholQR2) give an
-// orthonormal Q to working precision when M is not too ill conditioned.  A
-// pivot that falls below a relative threshold flags the problem, and the
-// Householder kernel recomputes that problem's Q from the original M.
+// GEMM, factor G = L L^T and form Q = M L^-T by block forward substitution.
+// Two passes (CholQR2) give an orthonormal Q to working precision when M is
+// not too ill conditioned.  A pivot that falls below a relative threshold
+// flags the problem, and the Householder kernel recomputes that problem's Q
+// from the original M.
 #include "common.hpp"
 #include "kernels.hpp"
+
+#include <algorithm>
 
 namespace rsvd {
 
@@ -29,87 +32,136 @@ __device__ __forceinline__ double ld_elem(const void* p, int elem, int64_t i)
 }
 
 // ---------------------------------------------------------------- Cholesky
-// One workgroup per problem; blocked left-looking, 16-column panels kept in LDS.
+// One workgroup per problem, G (l x l, FP64) = L L^T, left-looking by 16-column
+// panels.  The panel (rows J..l-1) lives in LDS; its update with the already
+// factored columns, P -= L[J:, :J] L[J:J+16, :J]^T, is an FP64 MFMA product
+// per 16-row tile; the panel is then factored in place with one barrier per
+// column (the column scaling is deferred to the end of the panel).  Finally
+// the 16 x 16 diagonal blocks of L are inverted (one thread per column) into
+// D, which the substitution kernel uses.
+constexpr int PSTR = CHOL_W + 1;
+
 __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ descs)
 {
-    extern __shared__ double smem[];
-    __shared__ double T[CHOL_W][64 + 1];
-    __shared__ int bad;
+    extern __shared__ double Pn[];  // rows x PSTR panel, later the diagonal blocks
+    __shared__ double gdiag[CHOL_W];
+    __shared__ double sq[CHOL_W];
     const QrDesc& d = descs[blockIdx.x];
     if (d.Qout == nullptr || *d.flag) return;
     const int l = d.l;
     const double* __restrict__ G = d.G;
     double* __restrict__ L = d.L;
-    double* Pn = smem;  // (l) x CHOL_W panel, row r = global row J + r
-    const int tid = threadIdx.x;
-    if (tid == 0) bad = 0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    bool bad = false;
 
     for (int J = 0; J < l; J += CHOL_W) {
         const int w = min(CHOL_W, l - J);
         const int rows = l - J;
         for (int e = tid; e < rows * CHOL_W; e += 256) {
             const int r = e / CHOL_W, c = e % CHOL_W;
-            Pn[e] = (c < w) ? G[(int64_t)(J + r) * l + J + c] : 0.0;
+            Pn[r * PSTR + c] = (c < w && c <= r) ? G[(int64_t)(J + r) * l + J + c] : 0.0;
         }
+        if (tid < CHOL_W) gdiag[tid] = (tid < w) ? G[(int64_t)(J + tid) * l + J + tid] : 1.0;
         __syncthreads();
-        // left-looking update with the already factored columns 0..J-1
-        for (int t0 = 0; t0 < J; t0 += 64) {
-            const int tw = min(64, J - t0);
-            for (int e = tid; e < CHOL_W * 64; e += 256) {
-                const int c = e / 64, tt = e % 64;
-                T[c][tt] = (c < w && tt < tw) ? L[(int64_t)(J + c) * l + t0 + tt] : 0.0;
-            }
-            __syncthreads();
-            for (int e = tid; e < rows * CHOL_W; e += 256) {
-                const int r = e / CHOL_W, c = e % CHOL_W;
-                if (c < w && r >= c) {
-                    const double* __restrict__ Lr = L + (int64_t)(J + r) * l + t0;
-                    double s = 0.0;
-                    for (int tt = 0; tt < tw; ++tt) s = fma(Lr[tt], T[c][tt], s);
-                    Pn[e] -= s;
+        // left-looking update with columns 0..J-1 (MFMA, one 16-row tile per task)
+        if (J > 0) {
+            const int nt = (rows + 15) / 16;
+            for (int ti = wave; ti < nt; ti += 4) {
+                const int ra = J + ti * 16 + l16;   // global row of the A operand
+                const int rb = J + l16;             // global row of the B operand (panel column)
+                dbl4 acc = {0, 0, 0, 0};
+                for (int k0 = 0; k0 < J; k0 += 16) {
+                    double av[4], bv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int kc = k0 + 4 * u + lq;
+                        av[u] = (ra < l) ? L[(int64_t)ra * l + kc] : 0.0;
+                        bv[u] = (l16 < w) ? L[(int64_t)rb * l + kc] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = ti * 16 + lq + 4 * r;
+                    if (i < rows && l16 <= i) Pn[i * PSTR + l16] -= acc[r];
                 }
             }
-            __syncthreads();
         }
-        // factor the panel column by column
+        __syncthreads();
+        // unblocked right-looking factorisation of the panel, scaling deferred:
+        // column c's pivot is the updated P[c][c]; P[r][cc] -= P[r][c] P[cc][c] / P[c][c]
         for (int c = 0; c < w; ++c) {
-            if (tid == 0) {
-                const double d0 = Pn[c * CHOL_W + c];
-                const double gjj = G[(int64_t)(J + c) * l + J + c];
-                if (!(d0 > CHOL_PIVOT_REL * gjj) || !(d0 < INFINITY)) bad = 1;
-                Pn[c * CHOL_W + c] = bad ? 1.0 : sqrt(d0);
+            const double dc = Pn[c * PSTR + c];
+            if (!(dc > CHOL_PIVOT_REL * gdiag[c]) || !(dc < INFINITY)) {
+                bad = true;  // uniform: every thread reads the same values
+                break;
             }
-            __syncthreads();
-            if (bad) break;
-            const double piv = Pn[c * CHOL_W + c];
-            for (int r = c + 1 + tid; r < rows; r += 256) Pn[r * CHOL_W + c] /= piv;
-            __syncthreads();
+            const double inv = 1.0 / dc;
             for (int e = tid; e < rows * CHOL_W; e += 256) {
                 const int r = e / CHOL_W, cc = e % CHOL_W;
-                if (cc > c && cc < w && r >= cc) Pn[e] -= Pn[r * CHOL_W + c] * Pn[cc * CHOL_W + c];
+                if (cc > c && cc < w && r >= cc) Pn[r * PSTR + cc] -= Pn[r * PSTR + c] * Pn[cc * PSTR + c] * inv;
             }
             __syncthreads();
         }
         if (bad) break;
+        if (tid < w) sq[tid] = sqrt(Pn[tid * PSTR + tid]);
+        __syncthreads();
         for (int e = tid; e < rows * CHOL_W; e += 256) {
             const int r = e / CHOL_W, c = e % CHOL_W;
-            if (c < w) L[(int64_t)(J + r) * l + J + c] = (r >= c) ? Pn[e] : 0.0;
+            if (c < w) L[(int64_t)(J + r) * l + J + c] = (c <= r) ? Pn[r * PSTR + c] / sq[c] : 0.0;
         }
         __syncthreads();
     }
+    if (bad) {
+        if (tid == 0) *d.flag = 1;
+        return;
+    }
+    // inverses of the diagonal blocks: D_I = L_II^-1 (16 x 16, zero padded)
+    const int nbk = (l + 15) / 16;
+    for (int e = tid; e < nbk * 256; e += 256) {
+        const int I = e / 256, i = (e / 16) % 16, j = e % 16;
+        const int gi = I * 16 + i, gj = I * 16 + j;
+        Pn[e] = (gi < l && gj < l && j <= i) ? L[(int64_t)gi * l + gj] : 0.0;
+    }
     __syncthreads();
-    if (tid == 0 && bad) *d.flag = 1;
+    for (int e = tid; e < nbk * 16; e += 256) {
+        const int I = e / 16, c = e % 16;
+        const double* Lb = Pn + I * 256;
+        double* D = d.D + (int64_t)I * 256;
+        const int w = min(16, l - I * 16);
+        double col[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            double v = 0.0;
+            if (c < w && r >= c && r < w) {
+                if (r == c) {
+                    v = 1.0 / Lb[r * 16 + r];
+                } else {
+                    double s0 = 0.0;
+#pragma unroll
+                    for (int t2 = 0; t2 < 16; ++t2)
+                        if (t2 >= c && t2 < r) s0 += Lb[r * 16 + t2] * col[t2];
+                    v = -s0 / Lb[r * 16 + r];
+                }
+            }
+            col[r] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) D[r * 16 + c] = col[r];
+    }
 }
 
 // ---------------------------------------------------------------- Q = M L^-T
-// Each workgroup owns 16 rows of M and runs a blocked forward substitution
-// L q^T = m^T for its rows (no explicit inverse).
-__global__ __launch_bounds__(256) void trsm_kernel(const QrDesc* __restrict__ descs,
-                                                   const int* __restrict__ row_begin, int nprob,
-                                                   int from_min)
+// One wave per 16 rows of M.  With Q^T = L^-1 M^T, block column C of Q^T is
+// D_C (M^T[C] - L[C, :C] Q^T[:C]); both products are FP64 MFMA chains, the
+// accumulator of the first feeding the second directly as its B operand.  The
+// wave's 16 rows of Q stay in LDS; no other wave reads them.
+__global__ __launch_bounds__(64) void trsm_kernel(const QrDesc* __restrict__ descs,
+                                                  const int* __restrict__ row_begin, int nprob, int from_min)
 {
-    extern __shared__ double smem[];
-    __shared__ double Ld[16][17];
+    extern __shared__ double Qs[];  // 16 x (l + 1)
     const int t = blockIdx.x;
     const int b = find_problem(row_begin, nprob, t);
     const QrDesc& d = descs[b];
@@ -119,10 +171,11 @@ __global__ __launch_bounds__(256) void trsm_kernel(const QrDesc* __restrict__ de
     const int r0 = (t - row_begin[b]) * 16;
     const int nr = min(16, rows - r0);
     const double* __restrict__ L = d.L;
-    double* Qs = smem;  // 16 x ldq
-    const int tid = threadIdx.x;
+    const double* __restrict__ D = d.D;
+    const int lane = threadIdx.x;
+    const int l16 = lane & 15, lq = lane >> 4;
 
-    for (int e = tid; e < 16 * l; e += 256) {
+    for (int e = lane; e < 16 * l; e += 64) {
         const int r = e / l, c = e % l;
         double v = 0.0;
         if (r < nr) {
@@ -133,33 +186,42 @@ __global__ __launch_bounds__(256) void trsm_kernel(const QrDesc* __restrict__ de
     }
     __syncthreads();
     for (int C0 = 0; C0 < l; C0 += 16) {
-        const int w = min(16, l - C0);
-        {
-            const int i = tid >> 4, j = tid & 15;
-            Ld[i][j] = (i < w && j < w) ? L[(int64_t)(C0 + i) * l + C0 + j] : 0.0;
+        // acc[r] = (M^T - L Q^T)[C0 + lq + 4r][l16]  (column index, row of M)
+        dbl4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = C0 + lq + 4 * r;
+            acc[r] = (c < l) ? Qs[l16 * ldq + c] : 0.0;
         }
-        {
-            const int r = tid >> 4, c = tid & 15;
-            if (r < nr && c < w && C0 > 0) {
-                const double* __restrict__ Lr = L + (int64_t)(C0 + c) * l;
-                const double* Qr = Qs + r * ldq;
-                double s = 0.0;
-                for (int t2 = 0; t2 < C0; ++t2) s = fma(Lr[t2], Qr[t2], s);
-                Qs[r * ldq + C0 + c] -= s;
+        const int ra = C0 + l16;  // row of L supplying the A operand
+        for (int k0 = 0; k0 < C0; k0 += 16) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int kc = k0 + 4 * u + lq;
+                av[u] = (ra < l) ? -L[(int64_t)ra * l + kc] : 0.0;
+                bv[u] = Qs[l16 * ldq + kc];
             }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+        }
+        // R = D_C * acc: accumulator register s is the B operand row 4 s + lane/16
+        dbl4 res = {0, 0, 0, 0};
+        const double* Dc = D + (int64_t)(C0 / 16) * 256;
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+            const double av = Dc[l16 * 16 + 4 * s2 + lq];
+            res = __builtin_amdgcn_mfma_f64_16x16x4f64(av, acc[s2], res, 0, 0, 0);
         }
         __syncthreads();
-        if (tid < nr) {
-            double* Qr = Qs + tid * ldq + C0;
-            for (int c = 0; c < w; ++c) {
-                double s = Qr[c];
-                for (int t2 = 0; t2 < c; ++t2) s -= Ld[c][t2] * Qr[t2];
-                Qr[c] = s / Ld[c][c];
-            }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = C0 + lq + 4 * r;
+            if (c < l) Qs[l16 * ldq + c] = res[r];
         }
         __syncthreads();
     }
-    for (int e = tid; e < nr * l; e += 256) {
+    for (int e = lane; e < nr * l; e += 64) {
         const int r = e / l, c = e % l;
         d.Qout[(int64_t)(r0 + r) * l + c] = Qs[r * ldq + c];
     }
@@ -256,24 +318,25 @@ __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restri
 hipError_t launch_chol(const QrDesc* d, int nprob, int max_l, hipStream_t s)
 {
     if (nprob <= 0) return hipSuccess;
-    const size_t lds = (size_t)max_l * CHOL_W * sizeof(double);
+    // panel (max_l x PSTR) and, afterwards, the diagonal blocks (ceil(max_l/16) x 256)
+    const size_t lds = (size_t)std::max(max_l * PSTR, (max_l + 15) / 16 * 256) * sizeof(double);
     hipLaunchKernelGGL(chol_kernel, dim3(nprob), dim3(256), lds, s, d);
     return hipGetLastError();
 }
 
-hipError_t launch_trsm(const QrDesc* d, const int* row_begin, int nprob, int total_blocks,
-                           int from_min, int max_l, hipStream_t s)
+hipError_t launch_trsm(const QrDesc* d, const int* row_begin, int nprob, int total_blocks, int from_min,
+                       int max_l, hipStream_t s)
 {
     if (total_blocks <= 0) return hipSuccess;
     const size_t lds = (size_t)16 * (max_l + 1) * sizeof(double);
-    hipLaunchKernelGGL(trsm_kernel, dim3(total_blocks), dim3(256), lds, s, d, row_begin, nprob, from_min);
+    hipLaunchKernelGGL(trsm_kernel, dim3(total_blocks), dim3(64), lds, s, d, row_begin, nprob, from_min);
     return hipGetLastError();
 }
 
 hipError_t init_qr_kernels()
 {
     hipError_t e = hipFuncSetAttribute((const void*)chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       CHOL_MAX_L * CHOL_W * (int)sizeof(double));
+                                       CHOL_MAX_L * PSTR * (int)sizeof(double));
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)trsm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                16 * (CHOL_MAX_L + 1) * (int)sizeof(double));
