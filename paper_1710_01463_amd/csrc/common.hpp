@@ -10,6 +10,13 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 #define RSVD_WAVE 64
 
+// Pointers read from descriptor tables are generic; casting them to the global
+// address space lets the compiler emit global_load/store instead of flat
+// accesses (which share the LDS wait counter and serialise with LDS traffic).
+#define GLB __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ GLB T* to_glb(T* p) { return (GLB T*)p; }
+template <typename T> __device__ __forceinline__ const GLB T* to_glb(const T* p) { return (const GLB T*)p; }
+
 // Element storage kinds used by kernel templates.
 enum ElemKind : int { EK_F64 = 0, EK_F32 = 1, EK_BF16 = 2 };
 

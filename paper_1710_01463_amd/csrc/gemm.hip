@@ -64,16 +64,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
     const int t = blockIdx.x;
     const int b = find_problem(tile_begin, nprob, t);
     const GemmDesc& d = descs[b];
-    if (d.skip && *d.skip) return;
+    if (d.skip && *to_glb(d.skip)) return;
     const int local = t - tile_begin[b];
     const int m0 = (local / d.tiles_n) * BM;
     const int n0 = (local % d.tiles_n) * BN;
     const int M = d.M, N = d.N, K = d.K;
     const int64_t lda = d.lda, ldx = d.ldx;
     const int transA = d.transA, transX = d.transX;
-    const TA* __restrict__ A = (const TA*)d.A;
-    const TX* __restrict__ X = (const TX*)d.X;
-    const int* __restrict__ gather = d.gather;
+    const GLB TA* __restrict__ A = (const GLB TA*)d.A;
+    const GLB TX* __restrict__ X = (const GLB TX*)d.X;
+    const GLB int* __restrict__ gather = to_glb(d.gather);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
     }
 
     // ---- epilogue
-    TC* __restrict__ C = (TC*)d.C;
+    GLB TC* __restrict__ C = (GLB TC*)d.C;
     const int64_t ldc = d.ldc;
     const int transC = d.transC, accumulate = d.accumulate;
 #pragma unroll

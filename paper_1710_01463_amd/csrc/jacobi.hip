@@ -27,27 +27,42 @@ __device__ __forceinline__ int rr_block(int pos, int round, int nb)
     return pos == 0 ? 0 : ((pos - 1 + round) % (nb - 1)) + 1;
 }
 
-// Rotation (c, s) that zeroes the (p, q) entry of a symmetric 2 x 2 block
-// [a g; g b] under x_p <- c x_p - s x_q, x_q <- s x_p + c x_q (the classical
-// Hestenes/Jacobi formula).  Identity when |g| <= tol sqrt(a b).
+// |g| > tol sqrt(a b), with a hardware square root (about 2^-22 relative):
+// the threshold only decides whether a rotation is worth doing.
+__device__ __forceinline__ bool jac_needs(double a, double b, double g, double tol)
+{
+    return a > 0.0 && b > 0.0 && fabs(g) > tol * (__builtin_amdgcn_sqrt(a) * __builtin_amdgcn_sqrt(b));
+}
+
+// Rotation (c, s) that (nearly) zeroes the (p, q) entry of a symmetric 2 x 2
+// block [a g; g b] under x_p <- c x_p - s x_q, x_q <- s x_p + c x_q, from the
+// classical Hestenes/Jacobi formula t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+// zeta = (b - a) / (2 g).  The angle may be approximate (hardware reciprocal
+// and square root): a slightly-off rotation leaves a tiny off-diagonal that
+// later rotations remove.  What must hold to working precision is c^2 + s^2 = 1,
+// so c = (1 + t^2)^(-1/2) is refined by two Newton steps.
 __device__ __forceinline__ void jac_rotation(double a, double b, double g, double tol, double& cs, double& sn)
 {
     cs = 1.0;
     sn = 0.0;
-    if (a > 0.0 && b > 0.0 && g * g > tol * tol * a * b) {
-        const double zeta = (b - a) / (2.0 * g);
+    if (jac_needs(a, b, g, tol)) {
+        const double zeta = (b - a) * __builtin_amdgcn_rcp(2.0 * g);
         double t;
         if (fabs(zeta) > 1e150)
-            t = 0.5 / zeta;
+            t = 0.5 * __builtin_amdgcn_rcp(zeta);
         else
-            t = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        cs = rsqrt(1.0 + t * t);
-        sn = cs * t;
+            t = copysign(1.0, zeta) * __builtin_amdgcn_rcp(fabs(zeta) + __builtin_amdgcn_sqrt(fma(zeta, zeta, 1.0)));
+        const double x = fma(t, t, 1.0);
+        double y = __builtin_amdgcn_rsq(x);
+        y = y * fma(-0.5 * x * y, y, 1.5);
+        y = y * fma(-0.5 * x * y, y, 1.5);
+        cs = y;
+        sn = y * t;
     }
 }
 
 // Loads the 32 x JCH chunk (rows via rowmap, columns c0..) of M into registers.
-__device__ __forceinline__ void load_chunk(double (&pre)[JPF], const double* __restrict__ M, int64_t ldm,
+__device__ __forceinline__ void load_chunk(double (&pre)[JPF], const GLB double* __restrict__ M, int64_t ldm,
                                            int ncols, int c0, const int* rowmap)
 {
     const int tid = threadIdx.x;
@@ -69,20 +84,53 @@ __device__ __forceinline__ void store_chunk(const double (&pre)[JPF], double (*X
     }
 }
 
-// rows of M (32 of them, via rowmap) <- Ps (32 x 32) * rows of M, in place;
-// the next chunk is prefetched into registers while the current one is used.
-__device__ void apply_rotation(double* __restrict__ M, int64_t ldm, int ncols, const int* rowmap,
+// The augmented rows [X | P] of the pair, JCH columns at a time: chunk ci < ncx
+// is columns ci*JCH.. of X, later chunks are columns of P.
+struct ChunkSeq {
+    GLB double* X;
+    GLB double* P;
+    int64_t ldx, ldp;
+    int C, R, ncx, nct;
+    __device__ void select(int ci, GLB double*& M, int64_t& ldm, int& ncols, int& c0) const
+    {
+        if (ci < ncx) {
+            M = X;
+            ldm = ldx;
+            ncols = C;
+            c0 = ci * JCH;
+        } else {
+            M = P;
+            ldm = ldp;
+            ncols = R;
+            c0 = (ci - ncx) * JCH;
+        }
+    }
+    __device__ void load(double (&pre)[JPF], int ci, const int* rowmap) const
+    {
+        GLB double* M;
+        int64_t ldm;
+        int ncols, c0;
+        select(ci, M, ldm, ncols, c0);
+        load_chunk(pre, M, ldm, ncols, c0, rowmap);
+    }
+};
+
+// rows <- Ps (32 x 32) * rows for every chunk of the sequence, in place; the
+// first chunk is already in pre, each next chunk is prefetched while the
+// current one is multiplied.
+__device__ void apply_rotation(const ChunkSeq& cs, double (&pre)[JPF], const int* rowmap,
                                double (*Ps)[JR + 1], double (*Xs)[JCH + 1])
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
-    double pre[JPF];
-    load_chunk(pre, M, ldm, ncols, 0, rowmap);
-    for (int c0 = 0; c0 < ncols; c0 += JCH) {
+    for (int ci = 0; ci < cs.nct; ++ci) {
         store_chunk(pre, Xs);
         __syncthreads();
-        if (c0 + JCH < ncols) load_chunk(pre, M, ldm, ncols, c0 + JCH, rowmap);
-        // 2 row tiles x (JCH / 16) column tiles; wave w takes column tiles w, w + 4, ...
+        if (ci + 1 < cs.nct) cs.load(pre, ci + 1, rowmap);
+        GLB double* M;
+        int64_t ldm;
+        int ncols, c0;
+        cs.select(ci, M, ldm, ncols, c0);
 #pragma unroll
         for (int tj = wave; tj < JCH / 16; tj += 4) {
             dbl4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
@@ -123,13 +171,14 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc* __rest
     const JacDesc& d = descs[b];
     const int nb = d.nb;
     if (round >= nb - 1) return;
-    if (sweep > 0 && d.rot[sweep - 1] == 0) return;
+    GLB int* __restrict__ rot = to_glb(d.rot);
+    if (sweep > 0 && rot[sweep - 1] == 0) return;
     const int pi = t - pair_begin[b];
     const int I = rr_block(pi, round, nb);
     const int J = rr_block(nb - 1 - pi, round, nb);
     const int R = d.R, C = d.C;
     const double tol = d.tol;
-    double* __restrict__ X = d.X;
+    GLB double* __restrict__ X = to_glb(d.X);
     const int64_t ldx = d.ldx;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -162,6 +211,18 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc* __rest
 #pragma unroll
         for (int r = 0; r < 4; ++r) Hbuf[0][wi * 16 + lq + 4 * r][wj * 16 + l16] = acc[r];
     }
+    // prefetch the first chunk of the rotation phase; it lands during the inner solve
+    ChunkSeq seq;
+    seq.X = X;
+    seq.P = to_glb(d.P);
+    seq.ldx = ldx;
+    seq.ldp = d.ldp;
+    seq.C = C;
+    seq.R = R;
+    seq.ncx = (C + JCH - 1) / JCH;
+    seq.nct = seq.ncx + (d.P ? (R + JCH - 1) / JCH : 0);
+    double pre[JPF];
+    seq.load(pre, 0, rowmap);
     __syncthreads();
     // symmetrise from the upper triangle, identity for P
     for (int e = tid; e < JR * JR; e += 256) {
@@ -174,12 +235,12 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc* __rest
         const int i = e / JR, j = e % JR;
         if (i < j) {
             const double a = Hbuf[0][i][i], c = Hbuf[0][j][j], g = Hbuf[0][i][j];
-            if (a > 0.0 && c > 0.0 && g * g > tol * tol * a * c) any_rot = 1;
+            if (jac_needs(a, c, g, tol)) any_rot = 1;
         }
     }
     __syncthreads();
     if (!any_rot) return;
-    if (tid == 0) d.rot[sweep] = 1;
+    if (tid == 0) rot[sweep] = 1;
 
     // ---- inner cyclic Jacobi on the 32 x 32 Gram matrix, parallel order.
     // Thread (pi_, pj_) owns the 2 x 2 block (pair pi_ rows) x (pair pj_ cols)
@@ -217,8 +278,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc* __rest
     }
 
     // ---- apply the accumulated rotation to the rows of X and of P
-    apply_rotation(X, ldx, C, rowmap, Ps, Xs);
-    if (d.P) apply_rotation(d.P, d.ldp, R, rowmap, Ps, Xs);
+    apply_rotation(seq, pre, rowmap, Ps, Xs);
 }
 
 hipError_t launch_jacobi_round(const JacDesc* d, const int* pair_begin, int nprob, int total_pairs,
@@ -242,14 +302,21 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinDesc* __restrict__
     __shared__ int kk_s;
     const FinDesc& d = descs[blockIdx.x];
     const int R = d.R, C = d.C;
-    const double* __restrict__ X = d.X;
+    const GLB double* __restrict__ X = to_glb(d.X);
+    const GLB double* __restrict__ Pm = to_glb(d.P);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     for (int i = wave; i < R; i += 4) {
         double s = 0.0;
-        for (int t = lane; t < C; t += 64) {
-            const double x = X[(int64_t)i * d.ldx + t];
-            s = fma(x, x, s);
+        for (int t0 = lane; t0 < C; t0 += 64 * 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = t0 + 64 * u;
+                v[u] = (t < C) ? X[(int64_t)i * d.ldx + t] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s = fma(v[u], v[u], s);
         }
         s = wave_sum(s);
         if (lane == 0) sig[i] = sqrt(s);
@@ -269,11 +336,11 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinDesc* __restrict__
     }
     __syncthreads();
     for (int j = tid; j < R; j += 256) {
-        d.sig[j] = sig[perm_s[j]];
-        d.perm[j] = perm_s[j];
+        to_glb(d.sig)[j] = sig[perm_s[j]];
+        to_glb(d.perm)[j] = perm_s[j];
     }
     if (tid == 0) {
-        const double normA2 = *d.normA2;
+        const double normA2 = *to_glb(d.normA2);
         const int k = d.k;
         int info = 0;
         int kk = 0;
@@ -321,38 +388,74 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinDesc* __restrict__
             }
             w = tail[kk];
         }
-        if (info == 0 && d.rot && d.rot[d.max_sweeps - 1] != 0) info = -5;  // sweep cap reached
+        if (info == 0 && d.rot && to_glb(d.rot)[d.max_sweeps - 1] != 0) info = -5;  // sweep cap reached
         kk_s = kk;
-        *d.w_out = w;
-        *d.kkept_out = kk;
-        *d.info_out = info;
+        *to_glb(d.w_out) = w;
+        *to_glb(d.kkept_out) = kk;
+        *to_glb(d.info_out) = info;
     }
     __syncthreads();
     const int kk = kk_s;
     const int k = d.k;
-    TO* __restrict__ S = (TO*)d.S;
-    TO* __restrict__ U = (TO*)d.U;
-    TO* __restrict__ VT = (TO*)d.VT;
+    GLB TO* __restrict__ S = (GLB TO*)d.S;
+    GLB TO* __restrict__ U = (GLB TO*)d.U;
+    GLB TO* __restrict__ VT = (GLB TO*)d.VT;
     for (int j = tid; j < k; j += 256) S[j] = (j < kk) ? (TO)sig[perm_s[j]] : (TO)0;
     const int n = d.n, m = d.m;
-    // right vectors
-    for (int j = 0; j < k; ++j) {
-        const int src = (j < kk) ? perm_s[j] : -1;
-        const double sj = (j < kk) ? sig[src] : 0.0;
-        const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
-        if (d.mode == 0 || d.mode == 1) {
-            for (int t = tid; t < n; t += 256)
-                VT[(int64_t)j * d.ldvt + t] = (src >= 0) ? (TO)(X[(int64_t)src * d.ldx + t] * inv) : (TO)0;
-        } else {
-            for (int t = tid; t < n; t += 256)
-                VT[(int64_t)j * d.ldvt + t] = (src >= 0) ? (TO)d.P[(int64_t)src * d.ldp + t] : (TO)0;
+    // right vectors (rows of VT) and, for the full SVD, left vectors: a flat
+    // index space over (j, t) with 8 loads in flight per thread
+    const int64_t nv = (int64_t)k * n;
+    for (int64_t base = tid; base < nv; base += 256 * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t e = base + 256 * u;
+            v[u] = 0.0;
+            if (e < nv) {
+                const int j = (int)(e / n), t = (int)(e % n);
+                if (j < kk) {
+                    const int src = perm_s[j];
+                    if (d.mode == 2) {
+                        v[u] = Pm[(int64_t)src * d.ldp + t];
+                    } else {
+                        const double sj = sig[src];
+                        v[u] = X[(int64_t)src * d.ldx + t] * (sj > 0.0 ? 1.0 / sj : 0.0);
+                    }
+                }
+            }
         }
-        if (d.mode == 1) {
-            for (int i = tid; i < m; i += 256)
-                U[(int64_t)i * d.ldu + j] = (src >= 0) ? (TO)d.P[(int64_t)src * d.ldp + i] : (TO)0;
-        } else if (d.mode == 2) {
-            for (int i = tid; i < m; i += 256)
-                U[(int64_t)i * d.ldu + j] = (src >= 0) ? (TO)(X[(int64_t)src * d.ldx + i] * inv) : (TO)0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t e = base + 256 * u;
+            if (e < nv) VT[(e / n) * d.ldvt + e % n] = (TO)v[u];
+        }
+    }
+    if (d.mode == 1 || d.mode == 2) {
+        const int64_t nu = (int64_t)k * m;
+        for (int64_t base = tid; base < nu; base += 256 * 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t e = base + 256 * u;
+                v[u] = 0.0;
+                if (e < nu) {
+                    const int j = (int)(e / m), i = (int)(e % m);
+                    if (j < kk) {
+                        const int src = perm_s[j];
+                        if (d.mode == 1) {
+                            v[u] = Pm[(int64_t)src * d.ldp + i];
+                        } else {
+                            const double sj = sig[src];
+                            v[u] = X[(int64_t)src * d.ldx + i] * (sj > 0.0 ? 1.0 / sj : 0.0);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t e = base + 256 * u;
+                if (e < nu) U[(e % m) * d.ldu + e / m] = (TO)v[u];
+            }
         }
     }
 }
@@ -376,9 +479,9 @@ __global__ __launch_bounds__(64) void signfix_kernel(const FinDesc* __restrict__
     const FinDesc& d = descs[b];
     const int j = t - col_begin[b];
     const int lane = threadIdx.x;
-    const int64_t kk = *d.kkept_out;
-    TO* __restrict__ U = (TO*)d.U;
-    TO* __restrict__ VT = (TO*)d.VT;
+    const int64_t kk = *to_glb(d.kkept_out);
+    GLB TO* __restrict__ U = (GLB TO*)d.U;
+    GLB TO* __restrict__ VT = (GLB TO*)d.VT;
     const int m = d.m, n = d.n;
     if (j >= kk) {
         for (int i = lane; i < m; i += 64) U[(int64_t)i * d.ldu + j] = (TO)0;
@@ -386,11 +489,19 @@ __global__ __launch_bounds__(64) void signfix_kernel(const FinDesc* __restrict__
     }
     double best = -1.0;
     int bi = 0x7fffffff;
-    for (int i = lane; i < m; i += 64) {
-        const double a = fabs((double)U[(int64_t)i * d.ldu + j]);
-        if (a > best) {
-            best = a;
-            bi = i;
+    for (int i0 = lane; i0 < m; i0 += 64 * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + 64 * u;
+            v[u] = (i < m) ? fabs((double)U[(int64_t)i * d.ldu + j]) : -1.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (v[u] > best) {
+                best = v[u];
+                bi = i0 + 64 * u;
+            }
         }
     }
 #pragma unroll

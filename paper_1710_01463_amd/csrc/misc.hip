@@ -7,7 +7,7 @@ namespace rsvd {
 
 template <typename T> __device__ __forceinline__ double ldv(const void* p, int64_t i)
 {
-    return to_f64(((const T*)p)[i]);
+    return to_f64(((const GLB T*)p)[i]);
 }
 __device__ __forceinline__ double load_elem(const void* p, int elem, int64_t i)
 {
@@ -18,11 +18,11 @@ __device__ __forceinline__ double load_elem(const void* p, int elem, int64_t i)
 __device__ __forceinline__ void store_elem(void* p, int elem, int64_t i, double v)
 {
     if (elem == E_F64)
-        ((double*)p)[i] = v;
+        ((GLB double*)p)[i] = v;
     else if (elem == E_F32)
-        ((float*)p)[i] = (float)v;
+        ((GLB float*)p)[i] = (float)v;
     else
-        ((__bf16*)p)[i] = from_f64<__bf16>(v);
+        ((GLB __bf16*)p)[i] = from_f64<__bf16>(v);
 }
 
 // ||A||_F^2 over a chunk of STAGE_ROWS rows (fixed reduction order), plus the
@@ -41,16 +41,24 @@ __global__ __launch_bounds__(256) void stage_kernel(const StageDesc* __restrict_
     const int n = d.n;
     const int tid = threadIdx.x;
     double s = 0.0;
-    for (int e = tid; e < nr * n; e += 256) {
-        const int i = r0 + e / n, j = e % n;
-        const double v = load_elem(d.A, d.a_elem, (int64_t)i * d.lda + j);
-        s = fma(v, v, s);
-        if (d.Acast) store_elem(d.Acast, d.cast_elem, (int64_t)i * n + j, v);
+    for (int base = tid; base < nr * n; base += 256 * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = base + 256 * u;
+            v[u] = (e < nr * n) ? load_elem(d.A, d.a_elem, (int64_t)(r0 + e / n) * d.lda + e % n) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = base + 256 * u;
+            s = fma(v[u], v[u], s);
+            if (d.Acast && e < nr * n) store_elem(d.Acast, d.cast_elem, (int64_t)(r0 + e / n) * n + e % n, v[u]);
+        }
     }
     s = wave_sum(s);
     if ((tid & 63) == 0) red[tid >> 6] = s;
     __syncthreads();
-    if (tid == 0) d.partial[c] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (tid == 0) to_glb(d.partial)[c] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 __global__ void stage_final_kernel(const StageDesc* __restrict__ descs, int nprob)
@@ -60,12 +68,12 @@ __global__ void stage_final_kernel(const StageDesc* __restrict__ descs, int npro
     const StageDesc& d = descs[b];
     double s = 0.0, c = 0.0;
     for (int i = 0; i < d.nchunks; ++i) {
-        const double x = d.partial[i];
+        const double x = to_glb(d.partial)[i];
         const double tsum = s + x;
         if (fabs(s) >= fabs(x)) c += (s - tsum) + x; else c += (x - tsum) + s;
         s = tsum;
     }
-    *d.normA2 = s + c;
+    *to_glb(d.normA2) = s + c;
 }
 
 hipError_t launch_stage(const StageDesc* d, const int* chunk_begin, int nprob, int total_chunks,
@@ -163,10 +171,10 @@ __global__ __launch_bounds__(256) void copy_f64_kernel(const CopyDesc* __restric
         const int r = e / 64, c = e % 64;
         if (!d.transpose) {
             const int gi = i0 + r, gj = j0 + c;
-            if (gi < d.m && gj < d.n) d.X[(int64_t)gi * d.ldx + gj] = T[r][c];
+            if (gi < d.m && gj < d.n) to_glb(d.X)[(int64_t)gi * d.ldx + gj] = T[r][c];
         } else {
             const int gj = j0 + r, gi = i0 + c;  // X row = column of A
-            if (gi < d.m && gj < d.n) d.X[(int64_t)gj * d.ldx + gi] = T[c][r];
+            if (gi < d.m && gj < d.n) to_glb(d.X)[(int64_t)gj * d.ldx + gi] = T[c][r];
         }
     }
 }
@@ -189,7 +197,7 @@ __global__ __launch_bounds__(256) void eye_kernel(const EyeDesc* __restrict__ de
     const int64_t R = d.R;
     if (idx >= R * R) return;
     const int64_t i = idx / R, j = idx % R;
-    d.P[i * d.ldp + j] = (i == j) ? 1.0 : 0.0;
+    to_glb(d.P)[i * d.ldp + j] = (i == j) ? 1.0 : 0.0;
 }
 
 hipError_t launch_eye(const EyeDesc* d, const int* blk_begin, int nprob, int total_blocks, hipStream_t s)

@@ -22,7 +22,7 @@ constexpr double CHOL_PIVOT_REL = 1e-13;
 
 template <typename T> __device__ __forceinline__ double ld_any(const void* p, int64_t i)
 {
-    return to_f64(((const T*)p)[i]);
+    return to_f64(((const GLB T*)p)[i]);
 }
 __device__ __forceinline__ double ld_elem(const void* p, int elem, int64_t i)
 {
@@ -32,25 +32,33 @@ __device__ __forceinline__ double ld_elem(const void* p, int elem, int64_t i)
 }
 
 // ---------------------------------------------------------------- Cholesky
-// One workgroup per problem, G (l x l, FP64) = L L^T, left-looking by 16-column
-// panels.  The panel (rows J..l-1) lives in LDS; its update with the already
-// factored columns, P -= L[J:, :J] L[J:J+16, :J]^T, is an FP64 MFMA product
-// per 16-row tile; the panel is then factored in place with one barrier per
-// column (the column scaling is deferred to the end of the panel).  Finally
-// the 16 x 16 diagonal blocks of L are inverted (one thread per column) into
-// D, which the substitution kernel uses.
+// One workgroup per problem: G (l x l, FP64) = L L^T, left-looking by
+// 16-column panels.  The factor is stored column-major (the buffer holds
+// R = L^T row-major), so that the MFMA operands L[row][k] for 16 consecutive
+// rows are contiguous.  Each thread keeps its panel rows (up to 4) in
+// registers; the update with the already factored columns,
+// P -= L[J:, :J] L[J:J+16, :J]^T, is an FP64 MFMA product per 16-row tile
+// exchanged through LDS; the panel is then factored in registers with one
+// barrier per column, in which the 16 rows of the diagonal block publish
+// their current column.  Finally the 16 x 16 diagonal blocks of L are inverted
+// (one thread per column) into D, used by the substitution kernel.
 constexpr int PSTR = CHOL_W + 1;
-
-__global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ descs)
+// NT threads (one panel row each, NT >= l), a template parameter so that small
+// problems do not pay for the registers and barriers of large ones.
+template <int NT>
+__global__ __launch_bounds__(NT) void chol_kernel(const QrDesc* __restrict__ descs)
 {
-    extern __shared__ double Pn[];  // rows x PSTR panel, later the diagonal blocks
+    constexpr int CH_ROWS = 1;
+    constexpr int NW = NT / 64;
+    extern __shared__ double Pn[];  // rows x PSTR update terms, later the diagonal blocks
+    __shared__ double pub[2][CHOL_W];
     __shared__ double gdiag[CHOL_W];
-    __shared__ double sq[CHOL_W];
+    __shared__ double sqs[CHOL_W];  // 1 / sqrt(pivot) of the panel columns
     const QrDesc& d = descs[blockIdx.x];
-    if (d.Qout == nullptr || *d.flag) return;
+    if (d.Qout == nullptr || *to_glb(d.flag)) return;
     const int l = d.l;
-    const double* __restrict__ G = d.G;
-    double* __restrict__ L = d.L;
+    const GLB double* __restrict__ G = to_glb((const double*)d.G);
+    GLB double* __restrict__ Rt = to_glb(d.L);  // Rt[c * l + r] = L[r][c]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
     bool bad = false;
@@ -58,98 +66,142 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ de
     for (int J = 0; J < l; J += CHOL_W) {
         const int w = min(CHOL_W, l - J);
         const int rows = l - J;
-        for (int e = tid; e < rows * CHOL_W; e += 256) {
-            const int r = e / CHOL_W, c = e % CHOL_W;
-            Pn[r * PSTR + c] = (c < w && c <= r) ? G[(int64_t)(J + r) * l + J + c] : 0.0;
-        }
         if (tid < CHOL_W) gdiag[tid] = (tid < w) ? G[(int64_t)(J + tid) * l + J + tid] : 1.0;
-        __syncthreads();
-        // left-looking update with columns 0..J-1 (MFMA, one 16-row tile per task)
+        // update terms with the factored columns 0..J-1 (MFMA), into LDS
         if (J > 0) {
             const int nt = (rows + 15) / 16;
-            for (int ti = wave; ti < nt; ti += 4) {
-                const int ra = J + ti * 16 + l16;   // global row of the A operand
-                const int rb = J + l16;             // global row of the B operand (panel column)
-                dbl4 acc = {0, 0, 0, 0};
+            const int rb = J + l16;  // B operand row (panel column l16)
+            for (int tb = 0; tb < nt; tb += 4 * NW) {
+                dbl4 acc[4];
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) acc[tt] = dbl4{0, 0, 0, 0};
                 for (int k0 = 0; k0 < J; k0 += 16) {
-                    double av[4], bv[4];
+                    double bv[4], av[4][4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int kc = k0 + 4 * u + lq;
-                        av[u] = (ra < l) ? L[(int64_t)ra * l + kc] : 0.0;
-                        bv[u] = (l16 < w) ? L[(int64_t)rb * l + kc] : 0.0;
+                        bv[u] = (l16 < w) ? Rt[(int64_t)kc * l + rb] : 0.0;
                     }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+                    for (int tt = 0; tt < 4; ++tt) {
+                        const int ti = tb + wave + NW * tt;
+                        const int ra = J + ti * 16 + l16;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int kc = k0 + 4 * u + lq;
+                            av[tt][u] = (ti < nt && ra < l) ? Rt[(int64_t)kc * l + ra] : 0.0;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int tt = 0; tt < 4; ++tt)
+                            acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[tt][u], bv[u], acc[tt], 0, 0, 0);
                 }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = ti * 16 + lq + 4 * r;
-                    if (i < rows && l16 <= i) Pn[i * PSTR + l16] -= acc[r];
+                for (int tt = 0; tt < 4; ++tt) {
+                    const int ti = tb + wave + NW * tt;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = ti * 16 + lq + 4 * r;
+                        if (ti < nt && i < rows) Pn[i * PSTR + l16] = acc[tt][r];
+                    }
                 }
             }
         }
         __syncthreads();
-        // unblocked right-looking factorisation of the panel, scaling deferred:
-        // column c's pivot is the updated P[c][c]; P[r][cc] -= P[r][c] P[cc][c] / P[c][c]
-        for (int c = 0; c < w; ++c) {
-            const double dc = Pn[c * PSTR + c];
-            if (!(dc > CHOL_PIVOT_REL * gdiag[c]) || !(dc < INFINITY)) {
-                bad = true;  // uniform: every thread reads the same values
-                break;
+        // panel rows of this thread, read column-wise from the symmetric G (coalesced)
+        double row[CH_ROWS][CHOL_W];
+#pragma unroll
+        for (int i = 0; i < CH_ROWS; ++i) {
+            const int r = tid + NT * i;
+#pragma unroll
+            for (int c = 0; c < CHOL_W; ++c)
+                row[i][c] = (r < rows && c < w && c <= r) ? G[(int64_t)(J + c) * l + J + r] : 0.0;
+        }
+        if (J > 0) {
+#pragma unroll
+            for (int i = 0; i < CH_ROWS; ++i) {
+                const int r = tid + NT * i;
+                if (r < rows) {
+#pragma unroll
+                    for (int c = 0; c < CHOL_W; ++c) row[i][c] -= Pn[r * PSTR + c];
+                }
             }
-            const double inv = 1.0 / dc;
-            for (int e = tid; e < rows * CHOL_W; e += 256) {
-                const int r = e / CHOL_W, cc = e % CHOL_W;
-                if (cc > c && cc < w && r >= cc) Pn[r * PSTR + cc] -= Pn[r * PSTR + c] * Pn[cc * PSTR + c] * inv;
+        }
+        // factor the panel in registers: column c's pivot is the current
+        // L'[c][c]; rows below lose l_rc l_cc' (scaling deferred to the end)
+#pragma unroll
+        for (int c = 0; c < CHOL_W; ++c) {
+            if (c < w && !bad) {
+                double* pb = pub[c & 1];
+                if (tid >= c && tid < w) pb[tid] = row[0][c];
+                __syncthreads();
+                const double dc = pb[c];
+                if (!(dc > CHOL_PIVOT_REL * gdiag[c]) || !(dc < INFINITY)) {
+                    bad = true;  // uniform: every thread read the same value
+                } else {
+                    const double inv = 1.0 / dc;
+                    if (tid == 0) sqs[c] = 1.0 / sqrt(dc);
+#pragma unroll
+                    for (int i = 0; i < CH_ROWS; ++i) {
+                        const int r = tid + NT * i;
+                        if (r > c && r < rows) {
+                            const double f = row[i][c] * inv;
+#pragma unroll
+                            for (int cc = c + 1; cc < CHOL_W; ++cc)
+                                if (cc < w && (r >= CHOL_W || cc <= r)) row[i][cc] -= f * pb[cc];
+                        }
+                    }
+                }
             }
-            __syncthreads();
         }
         if (bad) break;
-        if (tid < w) sq[tid] = sqrt(Pn[tid * PSTR + tid]);
-        __syncthreads();
-        for (int e = tid; e < rows * CHOL_W; e += 256) {
-            const int r = e / CHOL_W, c = e % CHOL_W;
-            if (c < w) L[(int64_t)(J + r) * l + J + c] = (c <= r) ? Pn[r * PSTR + c] / sq[c] : 0.0;
+        __syncthreads();  // sqs complete
+#pragma unroll
+        for (int i = 0; i < CH_ROWS; ++i) {
+            const int r = tid + NT * i;
+            if (r < rows) {
+#pragma unroll
+                for (int c = 0; c < CHOL_W; ++c)
+                    if (c < w) Rt[(int64_t)(J + c) * l + J + r] = (c <= r) ? row[i][c] * sqs[c] : 0.0;
+            }
         }
         __syncthreads();
     }
     if (bad) {
-        if (tid == 0) *d.flag = 1;
+        if (tid == 0) *to_glb(d.flag) = 1;
         return;
     }
-    // inverses of the diagonal blocks: D_I = L_II^-1 (16 x 16, zero padded)
+    // inverses of the diagonal blocks: D_I = L_II^-1 (16 x 16, zero padded).
+    // The blocks are staged in LDS with their reciprocal diagonals; each thread
+    // forms one column of one inverse by forward substitution (branch free:
+    // the column is zero above its diagonal, so the sums run over t < r).
     const int nbk = (l + 15) / 16;
-    for (int e = tid; e < nbk * 256; e += 256) {
+    double* idg = Pn + nbk * 256;
+    for (int e = tid; e < nbk * 256; e += NT) {
         const int I = e / 256, i = (e / 16) % 16, j = e % 16;
         const int gi = I * 16 + i, gj = I * 16 + j;
-        Pn[e] = (gi < l && gj < l && j <= i) ? L[(int64_t)gi * l + gj] : 0.0;
+        Pn[e] = (gi < l && gj < l && j <= i) ? Rt[(int64_t)gj * l + gi] : 0.0;
     }
+    for (int e = tid; e < nbk * 16; e += NT) idg[e] = (e < l) ? 1.0 / Rt[(int64_t)e * l + e] : 0.0;
     __syncthreads();
-    for (int e = tid; e < nbk * 16; e += 256) {
+    GLB double* __restrict__ Dg = to_glb(d.D);
+    for (int e = tid; e < nbk * 16; e += NT) {
         const int I = e / 16, c = e % 16;
         const double* Lb = Pn + I * 256;
-        double* D = d.D + (int64_t)I * 256;
-        const int w = min(16, l - I * 16);
+        const double* ib = idg + I * 16;
         double col[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            double v = 0.0;
-            if (c < w && r >= c && r < w) {
-                if (r == c) {
-                    v = 1.0 / Lb[r * 16 + r];
-                } else {
-                    double s0 = 0.0;
+            double s0 = 0.0;
 #pragma unroll
-                    for (int t2 = 0; t2 < 16; ++t2)
-                        if (t2 >= c && t2 < r) s0 += Lb[r * 16 + t2] * col[t2];
-                    v = -s0 / Lb[r * 16 + r];
-                }
-            }
-            col[r] = v;
+            for (int t2 = 0; t2 < r; ++t2) s0 = fma(Lb[r * 16 + t2], col[t2], s0);
+            const double v = (r == c) ? ib[r] : -s0 * ib[r];
+            col[r] = (r < c) ? 0.0 : v;
         }
 #pragma unroll
-        for (int r = 0; r < 16; ++r) D[r * 16 + c] = col[r];
+        for (int r = 0; r < 16; ++r) Dg[(int64_t)I * 256 + r * 16 + c] = col[r];
     }
 }
 
@@ -165,24 +217,35 @@ __global__ __launch_bounds__(64) void trsm_kernel(const QrDesc* __restrict__ des
     const int t = blockIdx.x;
     const int b = find_problem(row_begin, nprob, t);
     const QrDesc& d = descs[b];
-    if (d.Qout == nullptr || *d.flag) return;
+    if (d.Qout == nullptr || *to_glb(d.flag)) return;
     const int l = d.l, rows = d.rows;
     const int ldq = l + 1;
     const int r0 = (t - row_begin[b]) * 16;
     const int nr = min(16, rows - r0);
-    const double* __restrict__ L = d.L;
-    const double* __restrict__ D = d.D;
+    const GLB double* __restrict__ Rt = to_glb((const double*)d.L);  // Rt[k * l + r] = L[r][k]
+    const GLB double* __restrict__ D = to_glb((const double*)d.D);
+    GLB double* __restrict__ Qout = to_glb(d.Qout);
     const int lane = threadIdx.x;
     const int l16 = lane & 15, lq = lane >> 4;
 
-    for (int e = lane; e < 16 * l; e += 64) {
-        const int r = e / l, c = e % l;
-        double v = 0.0;
-        if (r < nr) {
-            const int64_t gi = (int64_t)(r0 + r) * l + c;
-            v = from_min ? ld_elem(d.Min, d.min_elem, gi) : d.Qout[gi];
+    // load the 16 rows (8 loads in flight per lane)
+    for (int base = lane; base < 16 * l; base += 64 * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = base + 64 * u;
+            const int r = e / l, c = e % l;
+            v[u] = 0.0;
+            if (e < 16 * l && r < nr) {
+                const int64_t gi = (int64_t)(r0 + r) * l + c;
+                v[u] = from_min ? ld_elem(d.Min, d.min_elem, gi) : Qout[gi];
+            }
         }
-        Qs[r * ldq + c] = v;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = base + 64 * u;
+            if (e < 16 * l) Qs[(e / l) * ldq + e % l] = v[u];
+        }
     }
     __syncthreads();
     for (int C0 = 0; C0 < l; C0 += 16) {
@@ -194,20 +257,21 @@ __global__ __launch_bounds__(64) void trsm_kernel(const QrDesc* __restrict__ des
             acc[r] = (c < l) ? Qs[l16 * ldq + c] : 0.0;
         }
         const int ra = C0 + l16;  // row of L supplying the A operand
-        for (int k0 = 0; k0 < C0; k0 += 16) {
-            double av[4], bv[4];
+        for (int k0 = 0; k0 < C0; k0 += 32) {
+            double av[8], bv[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 const int kc = k0 + 4 * u + lq;
-                av[u] = (ra < l) ? -L[(int64_t)ra * l + kc] : 0.0;
-                bv[u] = Qs[l16 * ldq + kc];
+                const bool ok = kc < C0;
+                av[u] = (ok && ra < l) ? -Rt[(int64_t)kc * l + ra] : 0.0;
+                bv[u] = ok ? Qs[l16 * ldq + kc] : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+            for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
         }
         // R = D_C * acc: accumulator register s is the B operand row 4 s + lane/16
         dbl4 res = {0, 0, 0, 0};
-        const double* Dc = D + (int64_t)(C0 / 16) * 256;
+        const GLB double* Dc = D + (int64_t)(C0 / 16) * 256;
 #pragma unroll
         for (int s2 = 0; s2 < 4; ++s2) {
             const double av = Dc[l16 * 16 + 4 * s2 + lq];
@@ -223,7 +287,7 @@ __global__ __launch_bounds__(64) void trsm_kernel(const QrDesc* __restrict__ des
     }
     for (int e = lane; e < nr * l; e += 64) {
         const int r = e / l, c = e % l;
-        d.Qout[(int64_t)(r0 + r) * l + c] = Qs[r * ldq + c];
+        Qout[(int64_t)(r0 + r) * l + c] = Qs[r * ldq + c];
     }
 }
 
@@ -250,9 +314,9 @@ __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restri
     __shared__ double beta_s[HH_MAXL];
     __shared__ double red[4];
     const QrDesc& d = descs[blockIdx.x];
-    if (d.Qout == nullptr || !*d.flag) return;
+    if (d.Qout == nullptr || !*to_glb(d.flag)) return;
     const int rows = d.rows, l = d.l;
-    double* __restrict__ A = d.Qout;
+    GLB double* __restrict__ A = to_glb(d.Qout);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     for (int64_t e = tid; e < (int64_t)rows * l; e += 256) A[e] = ld_elem(d.Min, d.min_elem, e);
@@ -318,9 +382,15 @@ __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restri
 hipError_t launch_chol(const QrDesc* d, int nprob, int max_l, hipStream_t s)
 {
     if (nprob <= 0) return hipSuccess;
-    // panel (max_l x PSTR) and, afterwards, the diagonal blocks (ceil(max_l/16) x 256)
-    const size_t lds = (size_t)std::max(max_l * PSTR, (max_l + 15) / 16 * 256) * sizeof(double);
-    hipLaunchKernelGGL(chol_kernel, dim3(nprob), dim3(256), lds, s, d);
+    // panel (max_l x PSTR) and, afterwards, the diagonal blocks with their
+    // reciprocal diagonals (ceil(max_l/16) x (256 + 16))
+    const size_t lds = (size_t)std::max(max_l * PSTR, (max_l + 15) / 16 * 272) * sizeof(double);
+    if (max_l <= 256)
+        hipLaunchKernelGGL(chol_kernel<256>, dim3(nprob), dim3(256), lds, s, d);
+    else if (max_l <= 512)
+        hipLaunchKernelGGL(chol_kernel<512>, dim3(nprob), dim3(512), lds, s, d);
+    else
+        hipLaunchKernelGGL(chol_kernel<1024>, dim3(nprob), dim3(1024), lds, s, d);
     return hipGetLastError();
 }
 
@@ -335,8 +405,12 @@ hipError_t launch_trsm(const QrDesc* d, const int* row_begin, int nprob, int tot
 
 hipError_t init_qr_kernels()
 {
-    hipError_t e = hipFuncSetAttribute((const void*)chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       CHOL_MAX_L * PSTR * (int)sizeof(double));
+    const int chol_lds = CHOL_MAX_L * PSTR * (int)sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void*)chol_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize, chol_lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)chol_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize, chol_lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)chol_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, chol_lds);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)trsm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                16 * (CHOL_MAX_L + 1) * (int)sizeof(double));
