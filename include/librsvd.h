@@ -132,6 +132,7 @@ typedef struct rsvd_plan rsvd_plan_t;
 #define RSVD_PLAN_FULLSVD 1u /* the plan runs fullsvd_truncate instead of the RSVD (p, q, seed ignored) */
 #define RSVD_PLAN_GRAPH 2u   /* capture the launch sequence into a HIP graph on first execute */
 #define RSVD_PLAN_SAVE 4u    /* keep every intermediate basis for rsvd_plan_backward */
+#define RSVD_PLAN_NO_REFINE 8u /* form B = Q^T A in the sketch precision instead of FP64 (accuracy study) */
 
 /* Validates the problems, sizes and allocates the plan's device workspace.
  * Returns RSVD_ERR_INVALID for bad problem descriptions. */

@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(_HERE, "librsvd.so")
 RSVD_OK, RSVD_ERR_INVALID, RSVD_ERR_ALLOC, RSVD_ERR_HIP, RSVD_ERR_NONFINITE, RSVD_ERR_NOCONV = 0, -1, -2, -3, -4, -5
 RSVD_F64, RSVD_F32 = 0, 1
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
-PLAN_FULLSVD, PLAN_GRAPH, PLAN_SAVE = 1, 2, 4
+PLAN_FULLSVD, PLAN_GRAPH, PLAN_SAVE, PLAN_NO_REFINE = 1, 2, 4, 8
 
 STATUS_NAMES = {0: "ok", -1: "invalid argument", -2: "allocation failed", -3: "HIP error",
                 -4: "non-finite input", -5: "Jacobi did not converge"}

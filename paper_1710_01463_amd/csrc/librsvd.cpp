@@ -410,7 +410,20 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
                 const double* Qf = wsp<double>(P, h.o_qstage[2 * h.q]);
                 d[b] = gd(Qf, h.l, 1, A[b], h.lda, 0, wsp<double>(P, h.o_b), h.n, h.l, (int)h.n, (int)h.m);
             }
-            P.g_b = add_gemm(B, GK_F64, E_F64, es, E_F64, d);
+            if ((P.flags & RSVD_PLAN_NO_REFINE) && P.prec != RSVD_PREC_F64) {
+                // B = Q^T A with the sketch arithmetic (operands rounded on load)
+                for (int b = 0; b < np; ++b) {
+                    const ProbHost& h = P.probs[b];
+                    if (P.need_cast) {
+                        d[b].X = wsp<char>(P, h.o_acast);
+                        d[b].ldx = h.n;
+                    }
+                }
+                const GemmKind gk2 = P.prec == RSVD_PREC_F32 ? GK_F32 : GK_BF16;
+                P.g_b = add_gemm(B, gk2, E_F64, P.need_cast ? P.e_sketch : es, E_F64, d);
+            } else {
+                P.g_b = add_gemm(B, GK_F64, E_F64, es, E_F64, d);
+            }
         }
     } else {
         std::vector<CopyDesc> d(np);

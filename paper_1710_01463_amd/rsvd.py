@@ -97,7 +97,7 @@ class Plan:
     """
 
     def __init__(self, problems, dtype=torch.float64, prec="f64", fullsvd=False, graph=True,
-                 save=False, device="cuda"):
+                 save=False, refine=True, device="cuda"):
         self.dtype = dtype
         self.device = torch.device(device)
         self.fullsvd = fullsvd
@@ -116,7 +116,7 @@ class Plan:
             arr[i].ldu = 0
             arr[i].ldvt = 0
         flags = (L.PLAN_FULLSVD if fullsvd else 0) | (L.PLAN_GRAPH if graph else 0) | \
-                (L.PLAN_SAVE if save else 0)
+                (L.PLAN_SAVE if save else 0) | (0 if refine else L.PLAN_NO_REFINE)
         h = ctypes.c_void_p()
         L.check(L.lib().rsvd_plan_create(arr, n, _DT[dtype], L.PREC[prec], flags, ctypes.byref(h)))
         self._h = h
