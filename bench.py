@@ -125,6 +125,25 @@ def main():
         "gemm_tflops": gemm_flops / (ms / 1e3) / 1e12,
     }
 
+    # per-phase breakdown (eager launches, HIP events on the plan's stream) and
+    # the roofline of the dominant kernel
+    prof = plan.profile(As)
+    result["phases_ms"] = {k: round(v[0], 4) for k, v in prof.items() if v[1] > 0}
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms_dom, n_dom, fl_dom = prof[dom]
+    kernel_of = {"jacobi": "jacobi_round_kernel", "sketch": "gemm_kernel", "gram": "gemm_kernel",
+                 "project": "gemm_kernel", "backproj": "gemm_kernel", "chol": "chol_kernel",
+                 "trsm": "trsm_kernel"}
+    # FP64 MFMA peak (the Jacobi rotations, Grams and the FP64 GEMMs run on FP64 MFMA)
+    peak = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}["f64" if dom != "sketch" else args.prec]
+    achieved = (fl_dom / n_dom) / (ms_dom / n_dom * 1e-3) / 1e12 if n_dom and ms_dom else 0.0
+    result["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                          "frac": achieved / peak, "traffic": None,
+                          "kernel": kernel_of.get(dom, dom), "phase": dom,
+                          "avg_launch_us": ms_dom / n_dom * 1e3 if n_dom else None,
+                          "launches_per_step": n_dom,
+                          "flops_per_launch": fl_dom / n_dom if n_dom else None}
+
     if not args.no_compare:
         # same-GPU full-SVD truncation on the same batch (FP64 Jacobi)
         log("[bench] full-SVD leg")

@@ -151,6 +151,34 @@ int rsvd_plan_execute(rsvd_plan_t* plan, const void* const* A, void* const* U, v
                       void* const* VT, double* discarded_weight, int64_t* k_kept, int* info,
                       void* stream);
 
+/* Phases reported by rsvd_plan_profile. */
+enum {
+    RSVD_PHASE_STAGE = 0,      /* ||A||_F^2 and the low-precision copy of A */
+    RSVD_PHASE_OMEGA = 1,      /* Gaussian test matrices */
+    RSVD_PHASE_SKETCH = 2,     /* Y = A Omega, A^T Q, A Z */
+    RSVD_PHASE_GRAM = 3,       /* Gram matrices of the Cholesky QR */
+    RSVD_PHASE_CHOL = 4,       /* Cholesky factorisations */
+    RSVD_PHASE_TRSM = 5,       /* Q = M L^-T */
+    RSVD_PHASE_HOUSEHOLDER = 6,
+    RSVD_PHASE_PROJECT = 7,    /* B = Q^T A */
+    RSVD_PHASE_JACOBI = 8,     /* block one-sided Jacobi rounds */
+    RSVD_PHASE_FINISH = 9,     /* norms, sort, truncation */
+    RSVD_PHASE_BACKPROJ = 10,  /* U = Q Utilde */
+    RSVD_PHASE_SIGNFIX = 11,
+    RSVD_PHASE_OTHER = 12,     /* fills, copies */
+    RSVD_NUM_PHASES = 13
+};
+
+/* rsvd_plan_profile -- one execute run without the graph, with HIP events
+ * around every launch on stream.  For each phase c < ncat: ms[c] = summed
+ * kernel time, launches[c] = number of launches, flops[c] = algorithmic FLOPs
+ * (GEMMs: 2 M N K per problem; Jacobi: 2 * 32 * 32 * C for every block-pair
+ * Gram formed plus 2 * 32 * 32 * (C + R) for every rotation applied; other
+ * phases 0).  Arguments otherwise as rsvd_plan_execute.  Blocking. */
+int rsvd_plan_profile(rsvd_plan_t* plan, const void* const* A, void* const* U, void* const* S,
+                      void* const* VT, double* discarded_weight, int64_t* k_kept, int* info,
+                      double* ms, int64_t* launches, double* flops, int ncat, void* stream);
+
 /* Device bytes of the plan's workspace. */
 int64_t rsvd_plan_workspace_bytes(const rsvd_plan_t* plan);
 

@@ -14,6 +14,9 @@ RSVD_F64, RSVD_F32 = 0, 1
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 PLAN_FULLSVD, PLAN_GRAPH, PLAN_SAVE, PLAN_NO_REFINE = 1, 2, 4, 8
 
+PHASES = ["stage", "omega", "sketch", "gram", "chol", "trsm", "householder", "project", "jacobi",
+          "finish", "backproj", "signfix", "other"]
+
 STATUS_NAMES = {0: "ok", -1: "invalid argument", -2: "allocation failed", -3: "HIP error",
                 -4: "non-finite input", -5: "Jacobi did not converge"}
 
@@ -60,6 +63,11 @@ def lib():
         L.rsvd_plan_execute.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                         ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _vp, _vp, _vp]
         L.rsvd_plan_execute.restype = ctypes.c_int
+        L.rsvd_plan_profile.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                        ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _vp, _vp,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_int, _vp]
+        L.rsvd_plan_profile.restype = ctypes.c_int
         L.rsvd_plan_workspace_bytes.argtypes = [_vp]
         L.rsvd_plan_workspace_bytes.restype = _i64
         L.rsvd_plan_destroy.argtypes = [_vp]

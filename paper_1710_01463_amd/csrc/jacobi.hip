@@ -239,6 +239,11 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc* __rest
         }
     }
     __syncthreads();
+    if (tid == 0) {
+        GLB int* st = to_glb(d.stats);
+        atomicAdd((int*)&st[0], 1);
+        if (any_rot) atomicAdd((int*)&st[1], 1);
+    }
     if (!any_rot) return;
     if (tid == 0) rot[sweep] = 1;
 

@@ -80,6 +80,7 @@ struct JacDesc {
     double* X;
     double* P;
     int* rot;          // per-sweep "rotated" flags, max_sweeps entries
+    int* stats;        // [0] block pairs whose Gram was formed, [1] rotations applied
     int64_t ldx, ldp;
     int R, C, nb;
     int pad_;

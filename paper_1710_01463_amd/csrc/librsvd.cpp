@@ -67,7 +67,7 @@ struct ProbHost {
     int mode;    // finish mode
     // workspace offsets (bytes)
     size_t o_acast, o_om, o_m[2], o_q[2], o_g, o_l1, o_l2, o_b, o_p, o_sig, o_perm, o_norm, o_part,
-        o_flags, o_rot, o_info_local;
+        o_flags, o_rot, o_stats, o_info_local;
     std::vector<size_t> o_mstage, o_qstage, o_l1stage, o_l2stage;  // l1/l2: inverse Cholesky factors
     size_t o_lwork, o_dwork;
     int nchunks;
@@ -78,6 +78,41 @@ struct GemmLaunch {
     Elem ea, ex, ec;
     size_t off_desc, off_begin;
     int total;
+    double flops;  // algorithmic 2 M N K summed over the problems
+};
+
+// Events around every launch of an eager execute (rsvd_plan_profile).
+struct Profiler {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> cat;
+    std::vector<double> flops;
+    size_t used = 0;
+    hipStream_t s = nullptr;
+    hipError_t begin(int c, double f)
+    {
+        if (ev.size() < 2 * (used + 1)) {
+            hipEvent_t a, b;
+            hipError_t e = hipEventCreate(&a);
+            if (e != hipSuccess) return e;
+            e = hipEventCreate(&b);
+            if (e != hipSuccess) return e;
+            ev.push_back(a);
+            ev.push_back(b);
+        }
+        if (cat.size() < used + 1) {
+            cat.push_back(c);
+            flops.push_back(f);
+        } else {
+            cat[used] = c;
+            flops[used] = f;
+        }
+        return hipEventRecord(ev[2 * used], s);
+    }
+    hipError_t end() { return hipEventRecord(ev[2 * used + 1], s), ++used, hipSuccess; }
+    ~Profiler()
+    {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
 };
 struct IdxLaunch {
     size_t off_desc, off_begin;
@@ -126,6 +161,7 @@ struct rsvd_plan {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    Profiler* prof = nullptr;  // set only during rsvd_plan_profile
 };
 
 namespace {
@@ -214,10 +250,11 @@ void layout(rsvd_plan& P)
     }
     // flags: per problem (2 q_max + 1) QR flags followed by max_sweeps rot flags
     P.off_flags_base = take(0);
-    const int per = (int)(2 * P.max_q + 1) + P.max_sweeps;
+    const int per = (int)(2 * P.max_q + 1) + P.max_sweeps + 2;
     for (size_t b = 0; b < P.probs.size(); ++b) {
         P.probs[b].o_flags = P.off_flags_base + sizeof(int) * (size_t)per * b;
         P.probs[b].o_rot = P.probs[b].o_flags + sizeof(int) * (size_t)(2 * P.max_q + 1);
+        P.probs[b].o_stats = P.probs[b].o_rot + sizeof(int) * (size_t)P.max_sweeps;
     }
     P.total_flags = per * (int)P.probs.size();
     off = align_up(P.off_flags_base + sizeof(int) * (size_t)P.total_flags, 256);
@@ -246,6 +283,9 @@ GemmLaunch add_gemm(Blob& B, GemmKind kind, Elem ea, Elem ex, Elem ec, std::vect
     g.off_desc = B.add(descs);
     g.off_begin = B.add(begin);
     g.total = begin.back();
+    g.flops = 0.0;
+    for (const GemmDesc& d : descs)
+        if (d.A != nullptr) g.flops += 2.0 * d.M * d.N * d.K;
     return g;
 }
 
@@ -463,6 +503,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             j.X = wsp<double>(P, h.o_b);
             j.P = wsp<double>(P, h.o_p);
             j.rot = wsp<int>(P, h.o_rot);
+            j.stats = wsp<int>(P, h.o_stats);
             j.ldx = h.C;
             j.ldp = h.R;
             j.R = h.R;
@@ -531,12 +572,22 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
         if (e_ != hipSuccess) return fail(RSVD_ERR_HIP, std::string("launch: ") + hipGetErrorString(e_)); \
     } while (0)
 
+// A launch of phase cat (RSVD_PHASE_*), timed when the plan is being profiled.
+#define PLAUNCH(cat, flops, x)                                                                   \
+    do {                                                                                          \
+        if (P.prof) LCHK(P.prof->begin((cat), (flops)));                                          \
+        LCHK(x);                                                                                  \
+        if (P.prof) LCHK(P.prof->end());                                                          \
+    } while (0)
+
 template <typename T> const T* dp(const rsvd_plan& P, size_t off) { return (const T*)(P.dblob + off); }
 
-int gemm(const rsvd_plan& P, const GemmLaunch& g, hipStream_t s)
+int gemm(const rsvd_plan& P, const GemmLaunch& g, hipStream_t s, int cat)
 {
-    LCHK(launch_gemm(g.kind, g.ea, g.ex, g.ec, dp<GemmDesc>(P, g.off_desc), dp<int>(P, g.off_begin), P.nprob,
-                     g.total, s));
+    if (g.total <= 0) return RSVD_OK;
+    PLAUNCH(cat, g.flops,
+            launch_gemm(g.kind, g.ea, g.ex, g.ec, dp<GemmDesc>(P, g.off_desc), dp<int>(P, g.off_begin), P.nprob,
+                        g.total, s));
     return RSVD_OK;
 }
 
@@ -545,52 +596,56 @@ int enqueue(rsvd_plan& P, hipStream_t s)
 {
     const int np = P.nprob;
     const int out_f64 = P.dt == RSVD_F64;
-    LCHK(launch_fill_i32(wsp<int>(P, P.off_one), 1, 1, s));
-    LCHK(launch_fill_i32(wsp<int>(P, P.off_flags_base), 0, P.total_flags, s));
-    LCHK(launch_stage(dp<StageDesc>(P, P.stage.off_desc), dp<int>(P, P.stage.off_begin), np, P.stage.total, s));
-    LCHK(launch_stage_final(dp<StageDesc>(P, P.stage.off_desc), np, s));
+    int rc;
+    PLAUNCH(RSVD_PHASE_OTHER, 0.0, launch_fill_i32(wsp<int>(P, P.off_one), 1, 1, s));
+    PLAUNCH(RSVD_PHASE_OTHER, 0.0, launch_fill_i32(wsp<int>(P, P.off_flags_base), 0, P.total_flags, s));
+    PLAUNCH(RSVD_PHASE_STAGE, 0.0,
+            launch_stage(dp<StageDesc>(P, P.stage.off_desc), dp<int>(P, P.stage.off_begin), np, P.stage.total, s));
+    PLAUNCH(RSVD_PHASE_STAGE, 0.0, launch_stage_final(dp<StageDesc>(P, P.stage.off_desc), np, s));
     if (!P.fullsvd) {
-        LCHK(launch_omega(dp<OmegaDesc>(P, P.omega.off_desc), dp<int>(P, P.omega.off_begin), np, P.omega.total,
-                          s));
+        PLAUNCH(RSVD_PHASE_OMEGA, 0.0,
+                launch_omega(dp<OmegaDesc>(P, P.omega.off_desc), dp<int>(P, P.omega.off_begin), np, P.omega.total, s));
         const int nst = 2 * P.max_q + 1;
         for (int st = 0; st < nst; ++st) {
-            int rc;
-            if ((rc = gemm(P, P.g_sketch[st], s)) != RSVD_OK) return rc;
+            if ((rc = gemm(P, P.g_sketch[st], s, RSVD_PHASE_SKETCH)) != RSVD_OK) return rc;
             const IdxLaunch& q1 = P.qr[2 * st];
             const IdxLaunch& q2 = P.qr[2 * st + 1];
             const IdxLaunch& t1 = P.trsm[2 * st];
             const IdxLaunch& t2 = P.trsm[2 * st + 1];
             // Cholesky QR pass 1
-            if ((rc = gemm(P, P.g_gram1[st], s)) != RSVD_OK) return rc;
-            LCHK(launch_chol(dp<QrDesc>(P, q1.off_desc), np, P.max_l, s));
-            LCHK(launch_trsm(dp<QrDesc>(P, t1.off_desc), dp<int>(P, t1.off_begin), np, t1.total, 1, P.max_l, s));
+            if ((rc = gemm(P, P.g_gram1[st], s, RSVD_PHASE_GRAM)) != RSVD_OK) return rc;
+            PLAUNCH(RSVD_PHASE_CHOL, 0.0, launch_chol(dp<QrDesc>(P, q1.off_desc), np, P.max_l, s));
+            PLAUNCH(RSVD_PHASE_TRSM, 0.0,
+                    launch_trsm(dp<QrDesc>(P, t1.off_desc), dp<int>(P, t1.off_begin), np, t1.total, 1, P.max_l, s));
             // pass 2 for the problems whose final basis this is
             if (t2.total > 0) {
-                if ((rc = gemm(P, P.g_gram2[st], s)) != RSVD_OK) return rc;
-                LCHK(launch_chol(dp<QrDesc>(P, q2.off_desc), np, P.max_l, s));
-                LCHK(launch_trsm(dp<QrDesc>(P, t2.off_desc), dp<int>(P, t2.off_begin), np, t2.total, 0, P.max_l,
-                                 s));
+                if ((rc = gemm(P, P.g_gram2[st], s, RSVD_PHASE_GRAM)) != RSVD_OK) return rc;
+                PLAUNCH(RSVD_PHASE_CHOL, 0.0, launch_chol(dp<QrDesc>(P, q2.off_desc), np, P.max_l, s));
+                PLAUNCH(RSVD_PHASE_TRSM, 0.0,
+                        launch_trsm(dp<QrDesc>(P, t2.off_desc), dp<int>(P, t2.off_begin), np, t2.total, 0, P.max_l, s));
             }
             // Householder for the problems whose Cholesky QR broke down
-            LCHK(launch_householder(dp<QrDesc>(P, q1.off_desc), np, s));
+            PLAUNCH(RSVD_PHASE_HOUSEHOLDER, 0.0, launch_householder(dp<QrDesc>(P, q1.off_desc), np, s));
         }
-        int rc;
-        if ((rc = gemm(P, P.g_b, s)) != RSVD_OK) return rc;
+        if ((rc = gemm(P, P.g_b, s, RSVD_PHASE_PROJECT)) != RSVD_OK) return rc;
     } else {
-        LCHK(launch_copy_f64(dp<CopyDesc>(P, P.copy.off_desc), dp<int>(P, P.copy.off_begin), np, P.copy.total, s));
+        PLAUNCH(RSVD_PHASE_OTHER, 0.0,
+                launch_copy_f64(dp<CopyDesc>(P, P.copy.off_desc), dp<int>(P, P.copy.off_begin), np, P.copy.total, s));
     }
-    LCHK(launch_eye(dp<EyeDesc>(P, P.eye.off_desc), dp<int>(P, P.eye.off_begin), np, P.eye.total, s));
+    PLAUNCH(RSVD_PHASE_OTHER, 0.0,
+            launch_eye(dp<EyeDesc>(P, P.eye.off_desc), dp<int>(P, P.eye.off_begin), np, P.eye.total, s));
     for (int sw = 0; sw < P.max_sweeps; ++sw)
         for (int r = 0; r < P.max_nb - 1; ++r)
-            LCHK(launch_jacobi_round(dp<JacDesc>(P, P.jac.off_desc), dp<int>(P, P.jac.off_begin), np, P.jac.total,
-                                     sw, r, s));
-    LCHK(launch_finish(dp<FinDesc>(P, P.finish.off_desc), np, out_f64, s));
+            PLAUNCH(RSVD_PHASE_JACOBI, 0.0,
+                    launch_jacobi_round(dp<JacDesc>(P, P.jac.off_desc), dp<int>(P, P.jac.off_begin), np, P.jac.total,
+                                        sw, r, s));
+    PLAUNCH(RSVD_PHASE_FINISH, 0.0, launch_finish(dp<FinDesc>(P, P.finish.off_desc), np, out_f64, s));
     if (!P.fullsvd) {
-        int rc;
-        if ((rc = gemm(P, P.g_u, s)) != RSVD_OK) return rc;
+        if ((rc = gemm(P, P.g_u, s, RSVD_PHASE_BACKPROJ)) != RSVD_OK) return rc;
     }
-    LCHK(launch_signfix(dp<FinDesc>(P, P.signfix.off_desc), dp<int>(P, P.signfix.off_begin), np,
-                        P.signfix.total, out_f64, s));
+    PLAUNCH(RSVD_PHASE_SIGNFIX, 0.0,
+            launch_signfix(dp<FinDesc>(P, P.signfix.off_desc), dp<int>(P, P.signfix.off_begin), np,
+                           P.signfix.total, out_f64, s));
     return RSVD_OK;
 }
 
@@ -620,13 +675,6 @@ int plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsv
     for (int64_t b = 0; b < batch; ++b) {
         int rc = validate_problem(probs[b], fullsvd);
         if (rc != RSVD_OK) return fail(rc, "problem " + std::to_string(b) + ": " + g_err);
-    }
-    {
-        static std::once_flag once;
-        static hipError_t init_err = hipSuccess;
-        std::call_once(once, [] { init_err = init_qr_kernels(); });
-        if (init_err != hipSuccess)
-            return fail(RSVD_ERR_HIP, std::string("kernel attributes: ") + hipGetErrorString(init_err));
     }
     rsvd_plan* P = new rsvd_plan();
     P->nprob = (int)batch;
@@ -674,6 +722,15 @@ int plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsv
         P->max_q = std::max<int>(P->max_q, (int)h.q);
     }
     layout(*P);
+    {
+        static std::once_flag once;
+        static hipError_t init_err = hipSuccess;
+        std::call_once(once, [] { init_err = init_qr_kernels(); });
+        if (init_err != hipSuccess) {
+            plan_free(P);
+            return fail(RSVD_ERR_HIP, std::string("kernel attributes: ") + hipGetErrorString(init_err));
+        }
+    }
     hipError_t e = hipMalloc(&P->ws, P->ws_bytes);
     if (e != hipSuccess) {
         plan_free(P);
@@ -908,6 +965,52 @@ int rsvd_philox4x32_10(const uint32_t* in, uint32_t* out, int64_t count, void* s
     g_err.clear();
     if (count < 0 || (count > 0 && (!in || !out))) return fail(RSVD_ERR_INVALID, "bad count or null");
     HIPCHK(launch_philox_words(in, out, count, (hipStream_t)stream));
+    return RSVD_OK;
+}
+
+int rsvd_plan_profile(rsvd_plan_t* plan, const void* const* A, void* const* U, void* const* S, void* const* VT,
+                      double* discarded_weight, int64_t* k_kept, int* info, double* ms, int64_t* launches,
+                      double* flops, int ncat, void* stream)
+{
+    g_err.clear();
+    if (!plan || !ms || !launches || !flops || ncat < 1) return fail(RSVD_ERR_INVALID, "null profile output");
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned saved = plan->flags;
+    plan->flags &= ~RSVD_PLAN_GRAPH;  // eager launches so that each can be timed
+    Profiler prof;
+    prof.s = s;
+    int rc = plan_execute(plan, A, U, S, VT, discarded_weight, k_kept, info, s);  // uploads descriptors
+    if (rc == RSVD_OK) {
+        plan->prof = &prof;
+        rc = enqueue(*plan, s);
+        plan->prof = nullptr;
+    }
+    plan->flags = saved;
+    if (rc != RSVD_OK) return rc;
+    HIPCHK(hipStreamSynchronize(s));
+    for (int c = 0; c < ncat; ++c) {
+        ms[c] = 0.0;
+        launches[c] = 0;
+        flops[c] = 0.0;
+    }
+    for (size_t i = 0; i < prof.used; ++i) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, prof.ev[2 * i], prof.ev[2 * i + 1]));
+        const int c = prof.cat[i];
+        if (c < ncat) {
+            ms[c] += t;
+            launches[c] += 1;
+            flops[c] += prof.flops[i];
+        }
+    }
+    // Jacobi work from the device counters of the profiled execute
+    if (RSVD_PHASE_JACOBI < ncat) {
+        std::vector<int> st(2);
+        for (const ProbHost& h : plan->probs) {
+            HIPCHK(hipMemcpy(st.data(), plan->ws + h.o_stats, 2 * sizeof(int), hipMemcpyDeviceToHost));
+            flops[RSVD_PHASE_JACOBI] += 2.0 * 32 * 32 * h.C * st[0] + 2.0 * 32 * 32 * ((double)h.C + h.R) * st[1];
+        }
+    }
     return RSVD_OK;
 }
 

@@ -150,6 +150,22 @@ class Plan:
                                           self.info.data_ptr(), _stream()))
         return self.outputs, self.w, self.k_kept, self.info
 
+    def profile(self, As):
+        """One execute without the graph, with HIP events around every launch.
+        Returns {phase: (ms, launches, algorithmic_flops)}.  Blocking."""
+        for A, pr in zip(As, self.problems):
+            if A.shape != (pr["m"], pr["n"]) or A.dtype != self.dtype:
+                raise ValueError("input matrix does not match its problem")
+        nc = len(L.PHASES)
+        ms = (ctypes.c_double * nc)()
+        nl = (ctypes.c_int64 * nc)()
+        fl = (ctypes.c_double * nc)()
+        aptr = L.ptr_array([A.data_ptr() for A in As])
+        L.check(L.lib().rsvd_plan_profile(self._h, aptr, self._ptrs[0], self._ptrs[1], self._ptrs[2],
+                                          self.w.data_ptr(), self.k_kept.data_ptr(), self.info.data_ptr(),
+                                          ms, nl, fl, nc, _stream()))
+        return {name: (ms[i], int(nl[i]), fl[i]) for i, name in enumerate(L.PHASES)}
+
     def close(self):
         if getattr(self, "_h", None):
             L.lib().rsvd_plan_destroy(self._h)
