@@ -53,6 +53,14 @@ def lib():
                                   ctypes.c_int64, ctypes.c_double, _dp, ctypes.c_int64,
                                   _dp, _dp, ctypes.c_int64, _dp, _i64p, _dp, _ip]
         L.orc_fullsvd.restype = ctypes.c_int
+        L.orc_rsvd_backward.argtypes = [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+                                        ctypes.c_double, _dp, _dp, _dp, ctypes.c_double, _dp]
+        L.orc_rsvd_backward.restype = ctypes.c_int
+        L.orc_fullsvd_backward.argtypes = [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_int64, ctypes.c_double, _dp, _dp, _dp,
+                                           ctypes.c_double, _dp]
+        L.orc_fullsvd_backward.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -135,3 +143,27 @@ def fullsvd(A, k, delta=0.0):
                            ctypes.byref(sw))
     return Result(U=U, S=S, VT=VT, w=w.value, k_kept=kk_out.value, status=st,
                   sig_all=sig, sweeps=sw.value)
+
+
+def rsvd_backward(A, k, p, q, seed, dU, dS, dVT, delta=0.0, broad=0.0):
+    """dA for L = <dU, U> + <dS, S> + <dVT, VT> of rsvd(A, k, p, q, seed, delta)."""
+    A = _f64(A)
+    m, n = A.shape
+    dA = np.empty((m, n))
+    st = lib().orc_rsvd_backward(_ptr(A), m, n, n, k, p, q, ctypes.c_uint64(seed), delta,
+                                 _ptr(_f64(dU)), _ptr(_f64(dS)), _ptr(_f64(dVT)), broad, _ptr(dA))
+    if st != OK:
+        raise RuntimeError(f"orc_rsvd_backward status {st}")
+    return dA
+
+
+def fullsvd_backward(A, k, dU, dS, dVT, delta=0.0, broad=0.0):
+    """dA of the same loss for the exact truncated SVD (reference gradient)."""
+    A = _f64(A)
+    m, n = A.shape
+    dA = np.empty((m, n))
+    st = lib().orc_fullsvd_backward(_ptr(A), m, n, n, k, delta, _ptr(_f64(dU)), _ptr(_f64(dS)),
+                                    _ptr(_f64(dVT)), broad, _ptr(dA))
+    if st != OK:
+        raise RuntimeError(f"orc_fullsvd_backward status {st}")
+    return dA

@@ -572,3 +572,337 @@ done:
     free(G); free(J); free(sig); free(wk); free(perm);
     return st;
 }
+
+/* ======================================================================== */
+/* Reverse-mode derivatives (adjoints), FP64, Gaussian test matrix fixed.   */
+/* The paper has no derivative; these follow the standard matrix-calculus  */
+/* results: the SVD adjoint (Townsend 2016, "Differentiating the singular  */
+/* value decomposition"; Seeger et al. 2017) with optional Lorentzian      */
+/* broadening of 1/(s_j^2 - s_i^2), the thin-QR adjoint (Walter & Lehmann  */
+/* 2018; Liao et al. 2019), and the product rule through every GEMM of     */
+/* Alg. RSVD.                                                              */
+/* ======================================================================== */
+
+/* C (M x N) = beta C + op(X) op(Y), op(X) M x K; tx/ty: 0 plain, 1 transposed */
+static void mm(int tx, int ty, int64_t M, int64_t N, int64_t K, const double *X, int64_t ldx,
+               const double *Y, int64_t ldy, double beta, double *C, int64_t ldc)
+{
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j < N; ++j) {
+            double s = 0.0;
+            for (int64_t t = 0; t < K; ++t) {
+                double a = tx ? X[t * ldx + i] : X[i * ldx + t];
+                double b = ty ? Y[j * ldy + t] : Y[t * ldy + j];
+                s += a * b;
+            }
+            C[i * ldc + j] = (beta == 0.0) ? s : beta * C[i * ldc + j] + s;  /* beta = 0 overwrites */
+        }
+}
+
+/* F_ij = 1/(s_j^2 - s_i^2) (i != j), broadened to d/(d^2 + eps); F_ii = 0 */
+static double fmat(double si, double sj, double eps)
+{
+    double d = sj * sj - si * si;
+    if (eps > 0.0) return d / (d * d + eps);
+    return d != 0.0 ? 1.0 / d : 0.0;
+}
+
+/*
+ * SVD adjoint for X (r x c, r <= c) = Ut diag(s) Vt^T with Ut (r x r)
+ * orthogonal, Vt (c x r) orthonormal columns, given cotangents Ub (r x r),
+ * sb (r), Vb (c x r).  Result Xb (r x c):
+ *   Xb = Ut [diag(sb) + J_U S + S J_V] Vt^T + Ut S^-1 Vb^T (I - Vt Vt^T),
+ *   J_U = F o (Ut^T Ub - Ub^T Ut),  J_V = F o (Vt^T Vb - Vb^T Vt).
+ * Rows with s_i = 0 take no S^-1 term.
+ */
+static void svd_adjoint_wide(int64_t r, int64_t c, const double *Ut, const double *s, const double *Vt,
+                             const double *Ub, const double *sb, const double *Vb, double eps,
+                             double *Xb)
+{
+    double *EU = (double *)malloc(sizeof(double) * r * r);
+    double *EV = (double *)malloc(sizeof(double) * r * r);
+    double *K = (double *)malloc(sizeof(double) * r * r);
+    double *N = (double *)malloc(sizeof(double) * r * c);
+    mm(1, 0, r, r, r, Ut, r, Ub, r, 0.0, EU, r);   /* Ut^T Ub */
+    mm(1, 0, r, r, c, Vt, r, Vb, r, 0.0, EV, r);   /* Vt^T Vb */
+    for (int64_t i = 0; i < r; ++i)
+        for (int64_t j = 0; j < r; ++j) {
+            double f = (i == j) ? 0.0 : fmat(s[i], s[j], eps);
+            double ju = f * (EU[i * r + j] - EU[j * r + i]);
+            double jv = f * (EV[i * r + j] - EV[j * r + i]);
+            K[i * r + j] = ((i == j) ? sb[i] : 0.0) + ju * s[j] + s[i] * jv;
+        }
+    /* N = K Vt^T + S^-1 (Vb^T - EV^T Vt^T) */
+    mm(0, 1, r, c, r, K, r, Vt, r, 0.0, N, c);
+    for (int64_t i = 0; i < r; ++i) {
+        if (!(s[i] > 0.0)) continue;
+        double inv = 1.0 / s[i];
+        for (int64_t t = 0; t < c; ++t) {
+            double v = Vb[t * r + i];
+            for (int64_t j = 0; j < r; ++j) v -= EV[j * r + i] * Vt[t * r + j];
+            N[i * c + t] += inv * v;
+        }
+    }
+    mm(0, 0, r, c, r, Ut, r, N, c, 0.0, Xb, c);
+    free(EU); free(EV); free(K); free(N);
+}
+
+/* Thin-QR adjoint: M = Q R (rows x l, R upper with positive diagonal), given
+ * Qb: Mb = (Qb + Q copyltu(-Qb^T Q)) R^-T, copyltu(X) = tril(X) + tril(X,-1)^T. */
+static void qr_adjoint(int64_t rows, int64_t l, const double *Q, const double *R, const double *Qb,
+                       double *Mb)
+{
+    double *C = (double *)malloc(sizeof(double) * l * l);
+    double *S = (double *)malloc(sizeof(double) * l * l);
+    mm(1, 0, l, l, rows, Qb, l, Q, l, 0.0, C, l); /* Qb^T Q */
+    for (int64_t i = 0; i < l; ++i)
+        for (int64_t j = 0; j < l; ++j) S[i * l + j] = -((i >= j) ? C[i * l + j] : C[j * l + i]);
+    double *X = (double *)malloc(sizeof(double) * rows * l);
+    memcpy(X, Qb, sizeof(double) * rows * l);
+    mm(0, 0, rows, l, l, Q, l, S, l, 1.0, X, l);
+    /* Mb R^T = X: back substitution per row */
+    for (int64_t i = 0; i < rows; ++i)
+        for (int64_t rr = l - 1; rr >= 0; --rr) {
+            double v = X[i * l + rr];
+            for (int64_t c = rr + 1; c < l; ++c) v -= Mb[i * l + c] * R[rr * l + c];
+            Mb[i * l + rr] = (R[rr * l + rr] != 0.0) ? v / R[rr * l + rr] : 0.0;
+        }
+    free(C); free(S); free(X);
+}
+
+/* Sorted thin factors of B^T's Jacobi result and the truncation/sign state
+ * of the forward, recomputed exactly as orc_rsvd does. */
+typedef struct {
+    int64_t m, n, kk, l, kkeep, nst;
+    double *Om, **M, **Q, **R, *Ut, *s, *Vt, *sgn;
+} rsvd_state;
+
+static void state_free(rsvd_state *st)
+{
+    if (st->M)
+        for (int64_t i = 0; i < st->nst; ++i) {
+            free(st->M[i]); free(st->Q[i]); free(st->R[i]);
+        }
+    free(st->M); free(st->Q); free(st->R);
+    free(st->Om); free(st->Ut); free(st->s); free(st->Vt); free(st->sgn);
+}
+
+static int rsvd_forward_state(const double *A, int64_t m, int64_t n, int64_t lda, int64_t k,
+                              int64_t p, int64_t q, uint64_t seed, double delta, rsvd_state *st)
+{
+    memset(st, 0, sizeof(*st));
+    int64_t mn = m < n ? m : n;
+    int64_t kk = k < mn ? k : mn;
+    int64_t l = kk + p < mn ? kk + p : mn;
+    int64_t nst = 2 * q + 1;
+    st->m = m; st->n = n; st->kk = kk; st->l = l; st->nst = nst;
+    double normA2 = frob2(A, m, n, lda);
+    if (!isfinite(normA2)) return ORC_ERR_NONFINITE;
+    st->Om = (double *)malloc(sizeof(double) * n * l);
+    st->M = (double **)calloc((size_t)nst, sizeof(double *));
+    st->Q = (double **)calloc((size_t)nst, sizeof(double *));
+    st->R = (double **)calloc((size_t)nst, sizeof(double *));
+    orc_gaussian(seed, n, l, st->Om);
+    for (int64_t s = 0; s < nst; ++s) {
+        int64_t rows = (s % 2 == 0) ? m : n;
+        st->M[s] = (double *)malloc(sizeof(double) * rows * l);
+        st->Q[s] = (double *)malloc(sizeof(double) * rows * l);
+        st->R[s] = (double *)malloc(sizeof(double) * l * l);
+        if (s == 0)
+            mat_a_x(m, n, l, A, lda, st->Om, st->M[s]);
+        else if (s % 2 == 1)
+            mat_at_x(m, n, l, A, lda, st->Q[s - 1], st->M[s]);
+        else
+            mat_a_x(m, n, l, A, lda, st->Q[s - 1], st->M[s]);
+        int rc = orc_hqr(rows, l, st->M[s], st->Q[s], st->R[s]);
+        if (rc != ORC_OK) return rc;
+    }
+    double *G = (double *)malloc(sizeof(double) * n * l);
+    double *J = (double *)malloc(sizeof(double) * l * l);
+    double *sig = (double *)malloc(sizeof(double) * l);
+    int64_t *perm = (int64_t *)malloc(sizeof(int64_t) * l);
+    double *wk = (double *)malloc(sizeof(double) * (kk + 1));
+    mat_at_x(m, n, l, A, lda, st->Q[nst - 1], G);
+    orc_jacobi_cols(n, l, G, J, 60, NULL);
+    for (int64_t j = 0; j < l; ++j) {
+        double s2 = 0.0;
+        for (int64_t t = 0; t < n; ++t) s2 += G[t * l + j] * G[t * l + j];
+        sig[j] = sqrt(s2);
+    }
+    sort_desc(l, sig, perm);
+    st->Ut = (double *)malloc(sizeof(double) * l * l);
+    st->Vt = (double *)malloc(sizeof(double) * n * l);
+    st->s = (double *)malloc(sizeof(double) * l);
+    st->sgn = (double *)malloc(sizeof(double) * l);
+    for (int64_t j = 0; j < l; ++j) {
+        int64_t c = perm[j];
+        st->s[j] = sig[c];
+        double inv = sig[c] > 0.0 ? 1.0 / sig[c] : 0.0;
+        for (int64_t r = 0; r < l; ++r) st->Ut[r * l + j] = J[r * l + c];
+        for (int64_t t = 0; t < n; ++t) st->Vt[t * l + j] = G[t * l + c] * inv;
+    }
+    {
+        orc_sum acc = {0.0, 0.0};
+        orc_sum_add(&acc, normA2);
+        wk[0] = normA2;
+        for (int64_t j = 1; j <= kk; ++j) {
+            orc_sum_add(&acc, -st->s[j - 1] * st->s[j - 1]);
+            double v = orc_sum_val(&acc);
+            wk[j] = v > 0.0 ? v : 0.0;
+        }
+    }
+    st->kkeep = choose_k(kk, delta, normA2, wk);
+    /* signs of the kept left vectors Q Ut[:, j] (largest magnitude positive) */
+    const double *Qf = st->Q[nst - 1];
+    for (int64_t j = 0; j < l; ++j) {
+        double best = -1.0, val = 0.0;
+        for (int64_t i = 0; i < m; ++i) {
+            double a = 0.0;
+            for (int64_t t = 0; t < l; ++t) a += Qf[i * l + t] * st->Ut[t * l + j];
+            if (fabs(a) > best) {
+                best = fabs(a);
+                val = a;
+            }
+        }
+        st->sgn[j] = (val < 0.0) ? -1.0 : 1.0;
+    }
+    free(G); free(J); free(sig); free(perm); free(wk);
+    return ORC_OK;
+}
+
+/*
+ * dA of L = <dU, U> + <dS, S> + <dVT, VT> for the outputs of orc_rsvd
+ * (U m x kk, S kk, VT kk x n, kk = min(k, m, n)), with Omega fixed by the seed.
+ * Cotangents of the zero-filled triplets beyond k_kept are ignored.
+ * broad: Lorentzian broadening eps = broad * sigma_1^4 (0 = exact).
+ */
+int orc_rsvd_backward(const double *A, int64_t m, int64_t n, int64_t lda, int64_t k, int64_t p,
+                      int64_t q, uint64_t seed, double delta, const double *dU, const double *dS,
+                      const double *dVT, double broad, double *dA)
+{
+    if (!A || !dU || !dS || !dVT || !dA || m < 1 || n < 1 || k < 1 || p < 0 || q < 0 || lda < n)
+        return ORC_ERR_INVALID;
+    rsvd_state st;
+    int rc = rsvd_forward_state(A, m, n, lda, k, p, q, seed, delta, &st);
+    if (rc != ORC_OK) {
+        state_free(&st);
+        return rc;
+    }
+    const int64_t l = st.l, kk = st.kk, kp = st.kkeep, nst = st.nst;
+    const double eps = broad * pow(st.s[0], 4);
+    double *Ub = (double *)calloc((size_t)(m * l), sizeof(double));  /* cotangent of Q Ut */
+    double *Vb = (double *)calloc((size_t)(n * l), sizeof(double));  /* cotangent of Vt */
+    double *sb = (double *)calloc((size_t)l, sizeof(double));
+    for (int64_t j = 0; j < kp; ++j) {
+        for (int64_t i = 0; i < m; ++i) Ub[i * l + j] = dU[i * kk + j] * st.sgn[j];
+        for (int64_t t = 0; t < n; ++t) Vb[t * l + j] = dVT[j * n + t] * st.sgn[j];
+        sb[j] = dS[j];
+    }
+    const double *Qf = st.Q[nst - 1];
+    double *Utb = (double *)malloc(sizeof(double) * l * l);
+    double *Bb = (double *)malloc(sizeof(double) * l * n);
+    double *Qb = (double *)malloc(sizeof(double) * (m > n ? m : n) * l);
+    double *Mb = (double *)malloc(sizeof(double) * (m > n ? m : n) * l);
+    /* U = Q Ut: Utb = Q^T Ub, Qb = Ub Ut^T */
+    mm(1, 0, l, l, m, Qf, l, Ub, l, 0.0, Utb, l);
+    mm(0, 1, m, l, l, Ub, l, st.Ut, l, 0.0, Qb, l);
+    /* SVD of B = Q^T A (l x n) */
+    svd_adjoint_wide(l, n, st.Ut, st.s, st.Vt, Utb, sb, Vb, eps, Bb);
+    /* B = Q^T A: Qb += A Bb^T, dA = Q Bb */
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < l; ++j) {
+            double v = 0.0;
+            for (int64_t t = 0; t < n; ++t) v += A[i * lda + t] * Bb[j * n + t];
+            Qb[i * l + j] += v;
+        }
+    mm(0, 0, m, n, l, Qf, l, Bb, n, 0.0, dA, n);
+    /* stages in reverse: M_s = Q_s R_s, M_s = A Q_{s-1} (even s > 0), A^T Q_{s-1} (odd), A Omega (s = 0) */
+    for (int64_t s = nst - 1; s >= 0; --s) {
+        int64_t rows = (s % 2 == 0) ? m : n;
+        qr_adjoint(rows, l, st.Q[s], st.R[s], Qb, Mb);
+        if (s % 2 == 0) {
+            const double *X = (s == 0) ? st.Om : st.Q[s - 1];  /* n x l */
+            mm(0, 1, m, n, l, Mb, l, X, l, 1.0, dA, n);         /* dA += Mb X^T */
+            if (s > 0) {                                        /* Qb_{s-1} = A^T Mb */
+                for (int64_t i = 0; i < n; ++i)
+                    for (int64_t j = 0; j < l; ++j) {
+                        double v = 0.0;
+                        for (int64_t t = 0; t < m; ++t) v += A[t * lda + i] * Mb[t * l + j];
+                        Qb[i * l + j] = v;
+                    }
+            }
+        } else {
+            const double *X = st.Q[s - 1];                      /* m x l */
+            mm(0, 1, m, n, l, X, l, Mb, l, 1.0, dA, n);         /* dA += Q_{s-1} Mb^T */
+            for (int64_t i = 0; i < m; ++i)                     /* Qb_{s-1} = A Mb */
+                for (int64_t j = 0; j < l; ++j) {
+                    double v = 0.0;
+                    for (int64_t t = 0; t < n; ++t) v += A[i * lda + t] * Mb[t * l + j];
+                    Qb[i * l + j] = v;
+                }
+        }
+    }
+    free(Ub); free(Vb); free(sb); free(Utb); free(Bb); free(Qb); free(Mb);
+    state_free(&st);
+    return ORC_OK;
+}
+
+/*
+ * Reference gradient of the exact truncated SVD (Alg. TSVD) for the same
+ * loss, by the SVD adjoint applied to A's full SVD (cotangents zero beyond
+ * k_kept).  Works on A (m <= n) or on A^T (m > n).
+ */
+int orc_fullsvd_backward(const double *A, int64_t m, int64_t n, int64_t lda, int64_t k, double delta,
+                         const double *dU, const double *dS, const double *dVT, double broad,
+                         double *dA)
+{
+    if (!A || !dU || !dS || !dVT || !dA || m < 1 || n < 1 || k < 1 || lda < n) return ORC_ERR_INVALID;
+    int64_t mn = m < n ? m : n, kk = k < mn ? k : mn;
+    double *U = (double *)malloc(sizeof(double) * m * kk);
+    double *S = (double *)malloc(sizeof(double) * kk);
+    double *VT = (double *)malloc(sizeof(double) * kk * n);
+    double *sall = (double *)malloc(sizeof(double) * mn);
+    double w;
+    int64_t kp;
+    /* full factors: U_f (m x mn), V_f (n x mn) from a full-rank truncation */
+    double *Uf = (double *)malloc(sizeof(double) * m * mn);
+    double *Sf = (double *)malloc(sizeof(double) * mn);
+    double *VTf = (double *)malloc(sizeof(double) * mn * n);
+    int rc = orc_fullsvd(A, m, n, lda, mn, 0.0, Uf, mn, Sf, VTf, n, &w, &kp, sall, NULL);
+    int rc2 = orc_fullsvd(A, m, n, lda, k, delta, U, kk, S, VT, n, &w, &kp, NULL, NULL);
+    if ((rc != ORC_OK && rc != ORC_ERR_NOCONV) || (rc2 != ORC_OK && rc2 != ORC_ERR_NOCONV)) {
+        free(U); free(S); free(VT); free(sall); free(Uf); free(Sf); free(VTf);
+        return rc != ORC_OK ? rc : rc2;
+    }
+    const double eps = broad * pow(Sf[0], 4);
+    /* the kept triplets of the truncated call equal the leading ones of the full call */
+    int tall = m > n;
+    int64_t r = mn, c = tall ? m : n;
+    double *Ut = (double *)malloc(sizeof(double) * r * r);
+    double *Vt = (double *)malloc(sizeof(double) * c * r);
+    double *Ub = (double *)calloc((size_t)(r * r), sizeof(double));
+    double *Vb = (double *)calloc((size_t)(c * r), sizeof(double));
+    double *sb = (double *)calloc((size_t)r, sizeof(double));
+    double *Xb = (double *)malloc(sizeof(double) * r * c);
+    /* wide form X = A (m <= n): Ut = U_f (m x m), Vt = V_f; tall form X = A^T: Ut = V_f, Vt = U_f */
+    for (int64_t i = 0; i < r; ++i)
+        for (int64_t j = 0; j < r; ++j) Ut[i * r + j] = tall ? VTf[j * n + i] : Uf[i * mn + j];
+    for (int64_t t = 0; t < c; ++t)
+        for (int64_t j = 0; j < r; ++j) Vt[t * r + j] = tall ? Uf[t * mn + j] : VTf[j * n + t];
+    for (int64_t j = 0; j < kp; ++j) {
+        sb[j] = dS[j];
+        if (!tall) {
+            for (int64_t i = 0; i < m; ++i) Ub[i * r + j] = dU[i * kk + j];
+            for (int64_t t = 0; t < n; ++t) Vb[t * r + j] = dVT[j * n + t];
+        } else {
+            for (int64_t i = 0; i < n; ++i) Ub[i * r + j] = dVT[j * n + i];
+            for (int64_t t = 0; t < m; ++t) Vb[t * r + j] = dU[t * kk + j];
+        }
+    }
+    svd_adjoint_wide(r, c, Ut, Sf, Vt, Ub, sb, Vb, eps, Xb);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j) dA[i * n + j] = tall ? Xb[j * c + i] : Xb[i * c + j];
+    free(U); free(S); free(VT); free(sall); free(Uf); free(Sf); free(VTf);
+    free(Ut); free(Vt); free(Ub); free(Vb); free(sb); free(Xb);
+    return ORC_OK;
+}
