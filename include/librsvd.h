@@ -131,7 +131,7 @@ typedef struct rsvd_plan rsvd_plan_t;
 
 #define RSVD_PLAN_FULLSVD 1u /* the plan runs fullsvd_truncate instead of the RSVD (p, q, seed ignored) */
 #define RSVD_PLAN_GRAPH 2u   /* capture the launch sequence into a HIP graph on first execute */
-#define RSVD_PLAN_SAVE 4u    /* keep every intermediate basis for rsvd_plan_backward */
+#define RSVD_PLAN_SAVE 4u    /* keep every intermediate basis and the adjoint workspace for rsvd_plan_backward */
 #define RSVD_PLAN_NO_REFINE 8u /* form B = Q^T A in the sketch precision instead of FP64 (accuracy study) */
 
 /* Validates the problems, sizes and allocates the plan's device workspace.
@@ -166,7 +166,9 @@ enum {
     RSVD_PHASE_BACKPROJ = 10,  /* U = Q Utilde */
     RSVD_PHASE_SIGNFIX = 11,
     RSVD_PHASE_OTHER = 12,     /* fills, copies */
-    RSVD_NUM_PHASES = 13
+    RSVD_PHASE_BW_GEMM = 13,   /* products of the reverse pass (rsvd_plan_backward) */
+    RSVD_PHASE_BW_SMALL = 14,  /* cotangent staging, adjoint core, triangular solves of the reverse pass */
+    RSVD_NUM_PHASES = 15
 };
 
 /* rsvd_plan_profile -- one execute run without the graph, with HIP events
@@ -178,6 +180,41 @@ enum {
 int rsvd_plan_profile(rsvd_plan_t* plan, const void* const* A, void* const* U, void* const* S,
                       void* const* VT, double* discarded_weight, int64_t* k_kept, int* info,
                       double* ms, int64_t* launches, double* flops, int ncat, void* stream);
+
+/* rsvd_plan_backward -- reverse-mode derivative of the most recent
+ * rsvd_plan_execute of a plan created with RSVD_PLAN_SAVE (RSVD plans only).
+ * The paper's method (Sec. II.B, Alg. RSVD) is differentiated with the Gaussian
+ * test matrix held fixed (it is a function of the seed only): the standard
+ * adjoint of the SVD of B = Q^T A, the thin-QR adjoint of every
+ * orthonormalisation, and the product rule through every GEMM.  For each
+ * problem it writes
+ *     dA = gradient over A of  <dU, U> + <dS, S> + <dVT, VT>
+ * for the outputs (U, S, VT) of that execute.
+ *   dU, dS, dVT  host arrays of batch device pointers: cotangents shaped like
+ *                U (m x k, leading dimension ldu), S (k) and VT (k x n, ldvt),
+ *                in the plan's dtype.  Entries of the triplets beyond k_kept
+ *                (whose outputs are constant zeros) are ignored.
+ *   dA           host array of batch device pointers, m x n with leading
+ *                dimension lda, the plan's dtype; overwritten.  Must not
+ *                overlap A or the cotangents.
+ *   broadening   >= 0.  The factor 1 / (s_j^2 - s_i^2) of the SVD adjoint is
+ *                replaced by d / (d^2 + eps), d = s_j^2 - s_i^2,
+ *                eps = broadening * s_1^4; 0 gives the exact adjoint, which
+ *                diverges as two kept singular values approach each other.
+ * The products run in FP64 on the stored A whatever the plan's precision.
+ * The forward's A and outputs must be unchanged since that execute, and the
+ * call must be stream-ordered after it.  Asynchronous on stream.  Returns
+ * RSVD_ERR_INVALID without a saved forward, for a negative or NaN
+ * broadening, or for null pointers. */
+int rsvd_plan_backward(rsvd_plan_t* plan, const void* const* dU, const void* const* dS,
+                       const void* const* dVT, void* const* dA, double broadening, void* stream);
+
+/* rsvd_plan_profile_backward -- rsvd_plan_backward without the graph, with
+ * HIP events around every launch; outputs as rsvd_plan_profile (phases
+ * RSVD_PHASE_BW_GEMM and RSVD_PHASE_BW_SMALL).  Blocking. */
+int rsvd_plan_profile_backward(rsvd_plan_t* plan, const void* const* dU, const void* const* dS,
+                               const void* const* dVT, void* const* dA, double broadening, double* ms,
+                               int64_t* launches, double* flops, int ncat, void* stream);
 
 /* Device bytes of the plan's workspace. */
 int64_t rsvd_plan_workspace_bytes(const rsvd_plan_t* plan);

@@ -3,6 +3,6 @@
 The heavy lifting is in the HIP library librsvd.so (include/librsvd.h); this
 package only marshals arguments and owns torch-allocated outputs.
 """
-from .rsvd import Plan, fullsvd_truncate, rsvd_truncate  # noqa: F401
+from .rsvd import Plan, RSVDFunction, fullsvd_truncate, rsvd, rsvd_batch, rsvd_truncate  # noqa: F401
 
-__all__ = ["rsvd_truncate", "fullsvd_truncate", "Plan"]
+__all__ = ["rsvd_truncate", "fullsvd_truncate", "Plan", "RSVDFunction", "rsvd", "rsvd_batch"]

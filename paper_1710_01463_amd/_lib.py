@@ -15,7 +15,7 @@ PREC = {"f64": 0, "f32": 1, "bf16": 2}
 PLAN_FULLSVD, PLAN_GRAPH, PLAN_SAVE, PLAN_NO_REFINE = 1, 2, 4, 8
 
 PHASES = ["stage", "omega", "sketch", "gram", "chol", "trsm", "householder", "project", "jacobi",
-          "finish", "backproj", "signfix", "other"]
+          "finish", "backproj", "signfix", "other", "bw_gemm", "bw_small"]
 
 STATUS_NAMES = {0: "ok", -1: "invalid argument", -2: "allocation failed", -3: "HIP error",
                 -4: "non-finite input", -5: "Jacobi did not converge"}
@@ -68,6 +68,13 @@ def lib():
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64),
                                         ctypes.POINTER(ctypes.c_double), ctypes.c_int, _vp]
         L.rsvd_plan_profile.restype = ctypes.c_int
+        _pp = ctypes.POINTER(_vp)
+        L.rsvd_plan_backward.argtypes = [_vp, _pp, _pp, _pp, _pp, ctypes.c_double, _vp]
+        L.rsvd_plan_backward.restype = ctypes.c_int
+        L.rsvd_plan_profile_backward.argtypes = [_vp, _pp, _pp, _pp, _pp, ctypes.c_double,
+                                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64),
+                                                 ctypes.POINTER(ctypes.c_double), ctypes.c_int, _vp]
+        L.rsvd_plan_profile_backward.restype = ctypes.c_int
         L.rsvd_plan_workspace_bytes.argtypes = [_vp]
         L.rsvd_plan_workspace_bytes.restype = _i64
         L.rsvd_plan_destroy.argtypes = [_vp]

@@ -488,8 +488,10 @@ __global__ __launch_bounds__(64) void signfix_kernel(const FinDesc* __restrict__
     GLB TO* __restrict__ U = (GLB TO*)d.U;
     GLB TO* __restrict__ VT = (GLB TO*)d.VT;
     const int m = d.m, n = d.n;
+    GLB double* __restrict__ sgn = to_glb(d.sgn);
     if (j >= kk) {
         for (int i = lane; i < m; i += 64) U[(int64_t)i * d.ldu + j] = (TO)0;
+        if (sgn && lane == 0) sgn[j] = 0.0;
         return;
     }
     double best = -1.0;
@@ -518,8 +520,12 @@ __global__ __launch_bounds__(64) void signfix_kernel(const FinDesc* __restrict__
             bi = oi;
         }
     }
-    if (bi >= m) return;  // no finite entry: leave the column as it is
+    if (bi >= m) {  // no finite entry: leave the column as it is
+        if (sgn && lane == 0) sgn[j] = 1.0;
+        return;
+    }
     const bool flip = (double)U[(int64_t)bi * d.ldu + j] < 0.0;
+    if (sgn && lane == 0) sgn[j] = flip ? -1.0 : 1.0;
     if (flip) {
         for (int i = lane; i < m; i += 64) U[(int64_t)i * d.ldu + j] = -U[(int64_t)i * d.ldu + j];
         for (int x = lane; x < n; x += 64) VT[(int64_t)j * d.ldvt + x] = -VT[(int64_t)j * d.ldvt + x];

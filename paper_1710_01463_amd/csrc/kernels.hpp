@@ -70,6 +70,13 @@ hipError_t launch_trsm(const QrDesc* d, const int* row_begin, int nprob, int tot
 hipError_t init_qr_kernels();
 // Householder QR of Min into Qout for the problems whose flag is set.
 hipError_t launch_householder(const QrDesc* d, int nprob, hipStream_t s);
+// Adjoint helpers on QrDesc fields: L holds R (l x l, row-major) = Q^T M of a
+// stage; tri_prep zeroes its strictly lower part and writes the diagonal-block
+// inverses of L = R^T into D.  trsm_upper replaces Qout (rows x l) by
+// Qout R^-T.  Problems with Qout == nullptr are skipped.
+hipError_t launch_tri_prep(const QrDesc* d, int nprob, int max_l, hipStream_t s);
+hipError_t launch_trsm_upper(const QrDesc* d, const int* row_begin, int nprob, int total_blocks, int max_l,
+                             hipStream_t s);
 
 // ---------------------------------------------------------------- block one-sided Jacobi
 // Orthogonalises the R rows of X (R x C, row-major, R <= C) by left rotations,
@@ -104,6 +111,7 @@ struct FinDesc {
     void* U;
     void* S;
     void* VT;
+    double* sgn;       // k: sign applied to triplet j (+-1), 0 beyond k_kept; may be null
     double* w_out;
     int64_t* kkept_out;
     int* info_out;
@@ -170,5 +178,44 @@ struct EyeDesc {
     int pad_;
 };
 hipError_t launch_eye(const EyeDesc* d, const int* blk_begin, int nprob, int total_blocks, hipStream_t s);
+
+// ---------------------------------------------------------------- adjoint
+// Elementwise steps of the reverse pass of one RSVD (cotangent staging, the
+// SVD-adjoint core matrix, the symmetrisation of the QR adjoint).  Row-major
+// FP64 buffers unless stated.
+struct BwDesc {
+    const void* dU;     // m x k (ldu), cotangent element type
+    const void* dS;     // k
+    const void* dVT;    // k x n (ldvt)
+    const double* X;    // rotated B, l x n (ld n): row perm[j] = sigma_j v_j^T
+    const double* P;    // accumulated rotations, l x l: row perm[j] = u_j^T (of B)
+    const double* sig;  // l, sorted descending
+    const int* perm;    // l
+    const double* sgn;  // k, from the forward's sign fix (0 beyond k_kept)
+    double* Ub;         // m x l   cotangent of Q Utilde (signs applied, zero beyond k_kept)
+    double* Vbt;        // l x n   cotangent of Vtilde^T; scaled in place to Sigma^-1 Vbar^T
+    double* Vts;        // l x n   sorted Vtilde^T
+    double* Ut;         // l x l   sorted Utilde
+    double* sb;         // l       cotangent of sigma
+    const double* EU;   // l x l   Utilde^T Utilde_bar
+    const double* EV;   // l x l   Vtilde^T Vbar
+    double* Kp;         // l x l   core matrix
+    const double* C;    // l x l   Qbar^T Q of a stage
+    double* S;          // l x l   -copyltu(C)
+    int64_t ldu, ldvt;
+    int m, n, l, k;
+    int elem;           // Elem of dU, dS, dVT
+    int pad_;
+    double broad;       // Lorentzian broadening eps = broad * sigma_1^4
+};
+// blk_begin: prefix sums of per-problem block counts, ceil(bw_*_elems / BW_ELEMS_PER_BLOCK).
+int64_t bw_prep_elems(int m, int n, int l);
+int64_t bw_core_elems(int n, int l);
+int64_t bw_sym_elems(int l);
+constexpr int BW_ELEMS_PER_BLOCK = 1024;
+hipError_t launch_bw_prep(const BwDesc* d, const int* blk_begin, int nprob, int total, int cot_f64,
+                          hipStream_t s);
+hipError_t launch_bw_core(const BwDesc* d, const int* blk_begin, int nprob, int total, hipStream_t s);
+hipError_t launch_bw_sym(const BwDesc* d, const int* blk_begin, int nprob, int total, hipStream_t s);
 
 }  // namespace rsvd

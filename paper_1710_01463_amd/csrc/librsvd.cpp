@@ -70,6 +70,9 @@ struct ProbHost {
         o_flags, o_rot, o_stats, o_info_local;
     std::vector<size_t> o_mstage, o_qstage, o_l1stage, o_l2stage;  // l1/l2: inverse Cholesky factors
     size_t o_lwork, o_dwork;
+    size_t o_sgn;  // k canonical signs written by the sign fix (0 beyond k_kept)
+    // reverse pass (RSVD_PLAN_SAVE only)
+    size_t o_bw_w[2], o_bw_vbt, o_bw_vts, o_bw_bb, o_bw_ut, o_bw_utb, o_bw_eu, o_bw_ev, o_bw_kp, o_bw_sb;
     int nchunks;
 };
 
@@ -162,6 +165,30 @@ struct rsvd_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     Profiler* prof = nullptr;  // set only during rsvd_plan_profile
+    uint64_t fwd_gen = 0;      // bumped whenever the forward descriptors are rebuilt
+    bool fwd_saved = false;    // a forward execute of a RSVD_PLAN_SAVE plan was enqueued
+    struct BwStage {
+        GemmLaunch c, qs, r, da, qprev;
+        IdxLaunch sym, tri, trsm;
+    };
+    struct Backward {
+        Blob hb;
+        char* dblob = nullptr;
+        char* hpinned = nullptr;
+        size_t bytes = 0;
+        hipEvent_t upload_done = nullptr;
+        bool upload_pending = false;
+        bool valid = false;
+        uint64_t gen = 0;
+        std::vector<const void*> ldU, ldS, ldVT;
+        std::vector<void*> ldA;
+        double broad = 0.0;
+        IdxLaunch prep, core;
+        GemmLaunch utb, qb0, eu, ev, nn, bb, qba, da0;
+        std::vector<BwStage> st;  // indexed by stage
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t gexec = nullptr;
+    } bw;
 };
 
 namespace {
@@ -209,6 +236,7 @@ void layout(rsvd_plan& P)
         h.o_perm = take(sizeof(int) * h.R);
         h.o_p = take(sizeof(double) * (size_t)h.R * h.R);
         h.o_info_local = take(sizeof(int));
+        h.o_sgn = take(sizeof(double) * h.k);
         if (P.fullsvd) {
             h.o_b = take(sizeof(double) * (size_t)h.R * h.C);
             continue;
@@ -247,6 +275,20 @@ void layout(rsvd_plan& P)
         }
         h.o_g = take(sizeof(double) * l * l);
         h.o_b = take(sizeof(double) * (size_t)h.R * h.C);
+        if (save) {
+            const int64_t mx = std::max(m, n);
+            h.o_bw_w[0] = take(sizeof(double) * mx * l);
+            h.o_bw_w[1] = take(sizeof(double) * mx * l);
+            h.o_bw_vbt = take(sizeof(double) * l * n);
+            h.o_bw_vts = take(sizeof(double) * l * n);
+            h.o_bw_bb = take(sizeof(double) * l * n);
+            h.o_bw_ut = take(sizeof(double) * l * l);
+            h.o_bw_utb = take(sizeof(double) * l * l);
+            h.o_bw_eu = take(sizeof(double) * l * l);
+            h.o_bw_ev = take(sizeof(double) * l * l);
+            h.o_bw_kp = take(sizeof(double) * l * l);
+            h.o_bw_sb = take(sizeof(double) * l);
+        }
     }
     // flags: per problem (2 q_max + 1) QR flags followed by max_sweeps rot flags
     P.off_flags_base = take(0);
@@ -532,6 +574,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             f.U = U[b];
             f.S = S[b];
             f.VT = VT[b];
+            f.sgn = wsp<double>(P, h.o_sgn);
             f.w_out = w + b;
             f.kkept_out = kk + b;
             f.info_out = info ? info + b : wsp<int>(P, h.o_info_local);
@@ -649,6 +692,260 @@ int enqueue(rsvd_plan& P, hipStream_t s)
     return RSVD_OK;
 }
 
+// ---------------------------------------------------------------- reverse pass
+// Descriptor tables of rsvd_plan_backward.  Per problem (l, m, n, final stage
+// f = 2q): the head stages the cotangents and forms Bbar, the cotangent of
+// B = Q_f^T A, by the SVD adjoint; then Qbar (cotangent of the current basis)
+// walks the stages backwards through the thin-QR adjoint and the products of
+// the power iteration, and every product that involves A adds its share of
+// dA.  The two (max(m, n) x l) work buffers alternate between Qbar and the
+// next stage's Qbar; the triangular solve works in place.
+void build_bw_blob(rsvd_plan& P, const void* const* dU, const void* const* dS, const void* const* dVT,
+                   void* const* dA, double broad)
+{
+    Blob B;
+    auto& W = P.bw;
+    const int np = P.nprob;
+    const int* one = wsp<int>(P, P.off_one);
+    const Elem es = P.e_store;
+    const GemmDesc none = gd(nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0, 0, 0, one);
+    std::vector<BwDesc> bd(np);
+    std::vector<int> cprep(np), ccore(np);
+    auto blocks = [](int64_t e) { return (int)((e + BW_ELEMS_PER_BLOCK - 1) / BW_ELEMS_PER_BLOCK); };
+    for (int b = 0; b < np; ++b) {
+        const ProbHost& h = P.probs[b];
+        BwDesc& d = bd[b];
+        memset(&d, 0, sizeof(d));
+        d.dU = dU[b];
+        d.dS = dS[b];
+        d.dVT = dVT[b];
+        d.X = wsp<double>(P, h.o_b);
+        d.P = wsp<double>(P, h.o_p);
+        d.sig = wsp<double>(P, h.o_sig);
+        d.perm = wsp<int>(P, h.o_perm);
+        d.sgn = wsp<double>(P, h.o_sgn);
+        d.Ub = wsp<double>(P, h.o_bw_w[1]);
+        d.Vbt = wsp<double>(P, h.o_bw_vbt);
+        d.Vts = wsp<double>(P, h.o_bw_vts);
+        d.Ut = wsp<double>(P, h.o_bw_ut);
+        d.sb = wsp<double>(P, h.o_bw_sb);
+        d.EU = wsp<double>(P, h.o_bw_eu);
+        d.EV = wsp<double>(P, h.o_bw_ev);
+        d.Kp = wsp<double>(P, h.o_bw_kp);
+        d.C = wsp<double>(P, h.o_bw_eu);
+        d.S = wsp<double>(P, h.o_bw_ev);
+        d.ldu = h.ldu;
+        d.ldvt = h.ldvt;
+        d.m = (int)h.m;
+        d.n = (int)h.n;
+        d.l = h.l;
+        d.k = (int)h.k;
+        d.elem = es;
+        d.broad = broad;
+        cprep[b] = blocks(bw_prep_elems(d.m, d.n, d.l));
+        ccore[b] = blocks(bw_core_elems(d.n, d.l));
+    }
+    W.prep = add_idx(B, bd, cprep);
+    W.core = add_idx(B, bd, ccore);
+    {
+        std::vector<GemmDesc> utb(np), qb0(np), eu(np), ev(np), nn(np), bb(np), qba(np), da0(np);
+        for (int b = 0; b < np; ++b) {
+            const ProbHost& h = P.probs[b];
+            const int l = h.l, m = (int)h.m, n = (int)h.n;
+            const double* Qf = wsp<double>(P, h.o_qstage[2 * h.q]);
+            double* W0 = wsp<double>(P, h.o_bw_w[0]);
+            double* Ub = wsp<double>(P, h.o_bw_w[1]);
+            double* Ut = wsp<double>(P, h.o_bw_ut);
+            double* Utb = wsp<double>(P, h.o_bw_utb);
+            double* Vbt = wsp<double>(P, h.o_bw_vbt);
+            double* Vts = wsp<double>(P, h.o_bw_vts);
+            double* Bb = wsp<double>(P, h.o_bw_bb);
+            // U = Q Utilde:  Utilde_bar = Q^T Ubar,  Qbar = Ubar Utilde^T
+            utb[b] = gd(Qf, l, 1, Ub, l, 0, Utb, l, l, l, m);
+            qb0[b] = gd(Ub, l, 0, Ut, l, 1, W0, l, m, l, l);
+            // SVD of B:  EU = Utilde^T Utilde_bar,  EV = Vtilde^T Vbar
+            eu[b] = gd(Ut, l, 1, Utb, l, 0, wsp<double>(P, h.o_bw_eu), l, l, l, l);
+            ev[b] = gd(Vts, n, 0, Vbt, n, 1, wsp<double>(P, h.o_bw_ev), l, l, l, n);
+            // N = Kp Vtilde^T + Sigma^-1 Vbar^T (the second term staged by the core kernel), Bbar = Utilde N
+            nn[b] = gd(wsp<double>(P, h.o_bw_kp), l, 0, Vts, n, 0, Vbt, n, l, n, l);
+            nn[b].accumulate = 1;
+            bb[b] = gd(Ut, l, 0, Vbt, n, 0, Bb, n, l, n, l);
+            // B = Q^T A:  Qbar += A Bbar^T,  dA = Q Bbar
+            qba[b] = gd(P.lastA[b], h.lda, 0, Bb, n, 1, W0, l, m, l, n);
+            qba[b].accumulate = 1;
+            da0[b] = gd(Qf, l, 0, Bb, n, 0, dA[b], h.lda, m, n, l);
+        }
+        W.utb = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, utb);
+        W.qb0 = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, qb0);
+        W.eu = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, eu);
+        W.ev = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, ev);
+        W.nn = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, nn);
+        W.bb = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, bb);
+        W.qba = add_gemm(B, GK_F64, es, E_F64, E_F64, qba);
+        W.da0 = add_gemm(B, GK_F64, E_F64, E_F64, es, da0);
+    }
+    const int nst = 2 * P.max_q + 1;
+    W.st.assign(nst, rsvd_plan::BwStage());
+    for (int s = nst - 1; s >= 0; --s) {
+        std::vector<GemmDesc> c(np, none), qs(np, none), r(np, none), da(np, none), qprev(np, none);
+        std::vector<BwDesc> sym(bd);
+        std::vector<QrDesc> tri(np);
+        std::vector<int> csym(np, 0), ctri(np, 1), ctrsm(np, 0);
+        for (int b = 0; b < np; ++b) {
+            const ProbHost& h = P.probs[b];
+            memset(&tri[b], 0, sizeof(QrDesc));
+            tri[b].flag = const_cast<int*>(one);
+            tri[b].l = h.l;
+            if (s > 2 * h.q) continue;
+            const int l = h.l, m = (int)h.m, n = (int)h.n;
+            const int rows = (s % 2 == 0) ? m : n;
+            const int cur = (int)((2 * h.q - s) % 2);
+            double* Qb = wsp<double>(P, h.o_bw_w[cur]);
+            double* Qn = wsp<double>(P, h.o_bw_w[1 - cur]);
+            const double* Qs = wsp<double>(P, h.o_qstage[s]);
+            const void* Ms = wsp<char>(P, h.o_mstage[s]);
+            double* Cm = wsp<double>(P, h.o_bw_eu);
+            double* Sm = wsp<double>(P, h.o_bw_ev);
+            double* R = wsp<double>(P, h.o_lwork);
+            // thin QR M_s = Q_s R_s:  Mbar = (Qbar + Q_s copyltu(-Qbar^T Q_s)) R_s^-T
+            c[b] = gd(Qb, l, 1, Qs, l, 0, Cm, l, l, l, rows);
+            csym[b] = blocks(bw_sym_elems(l));
+            qs[b] = gd(Qs, l, 0, Sm, l, 0, Qb, l, rows, l, l);
+            qs[b].accumulate = 1;
+            r[b] = gd(Qs, l, 1, Ms, l, 0, R, l, l, l, rows);
+            tri[b].Qout = Qb;
+            tri[b].L = R;
+            tri[b].D = wsp<double>(P, h.o_dwork);
+            tri[b].rows = rows;
+            ctrsm[b] = (rows + 15) / 16;
+            // the product that formed M_s
+            if (s % 2 == 0) {
+                // M_s = A X_s, X_s = Omega (s = 0) or the previous basis: dA += Mbar X_s^T, Qbar_prev = A^T Mbar
+                const void* Xs = (s == 0) ? (const void*)wsp<char>(P, h.o_om) : wsp<double>(P, h.o_qstage[s - 1]);
+                da[b] = gd(Qb, l, 0, Xs, l, 1, dA[b], h.lda, m, n, l);
+                if (s > 0) qprev[b] = gd(P.lastA[b], h.lda, 1, Qb, l, 0, Qn, l, n, l, m);
+            } else {
+                // M_s = A^T Q_{s-1}: dA += Q_{s-1} Mbar^T, Qbar_prev = A Mbar
+                da[b] = gd(wsp<double>(P, h.o_qstage[s - 1]), l, 0, Qb, l, 1, dA[b], h.lda, m, n, l);
+                qprev[b] = gd(P.lastA[b], h.lda, 0, Qb, l, 0, Qn, l, m, l, n);
+            }
+            da[b].accumulate = 1;
+        }
+        rsvd_plan::BwStage& st = W.st[s];
+        st.c = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, c);
+        st.sym = add_idx(B, sym, csym);
+        st.qs = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, qs);
+        st.r = add_gemm(B, GK_F64, E_F64, P.e_y, E_F64, r);
+        st.tri = add_idx(B, tri, ctri);
+        st.trsm = add_idx(B, tri, ctrsm);
+        st.da = add_gemm(B, GK_F64, E_F64, (s == 0) ? P.e_sketch : E_F64, es, da);
+        st.qprev = add_gemm(B, GK_F64, es, E_F64, E_F64, qprev);
+    }
+    W.hb = std::move(B);
+}
+
+int enqueue_backward(rsvd_plan& P, hipStream_t s)
+{
+    const int np = P.nprob;
+    auto& W = P.bw;
+    const char* base = W.dblob;
+    auto dd = [&](size_t off) { return (const void*)(base + off); };
+    auto bgemm = [&](const GemmLaunch& g) -> int {
+        if (g.total <= 0) return RSVD_OK;
+        PLAUNCH(RSVD_PHASE_BW_GEMM, g.flops,
+                launch_gemm(g.kind, g.ea, g.ex, g.ec, (const GemmDesc*)dd(g.off_desc), (const int*)dd(g.off_begin),
+                            np, g.total, s));
+        return RSVD_OK;
+    };
+    int rc;
+    const int cot_f64 = P.dt == RSVD_F64;
+    PLAUNCH(RSVD_PHASE_BW_SMALL, 0.0,
+            launch_bw_prep((const BwDesc*)dd(W.prep.off_desc), (const int*)dd(W.prep.off_begin), np, W.prep.total,
+                           cot_f64, s));
+    for (const GemmLaunch* g : {&W.utb, &W.qb0, &W.eu, &W.ev})
+        if ((rc = bgemm(*g)) != RSVD_OK) return rc;
+    PLAUNCH(RSVD_PHASE_BW_SMALL, 0.0,
+            launch_bw_core((const BwDesc*)dd(W.core.off_desc), (const int*)dd(W.core.off_begin), np, W.core.total, s));
+    for (const GemmLaunch* g : {&W.nn, &W.bb, &W.qba, &W.da0})
+        if ((rc = bgemm(*g)) != RSVD_OK) return rc;
+    for (int st = (int)W.st.size() - 1; st >= 0; --st) {
+        const rsvd_plan::BwStage& S = W.st[st];
+        if ((rc = bgemm(S.c)) != RSVD_OK) return rc;
+        PLAUNCH(RSVD_PHASE_BW_SMALL, 0.0,
+                launch_bw_sym((const BwDesc*)dd(S.sym.off_desc), (const int*)dd(S.sym.off_begin), np, S.sym.total, s));
+        if ((rc = bgemm(S.qs)) != RSVD_OK) return rc;
+        if ((rc = bgemm(S.r)) != RSVD_OK) return rc;
+        PLAUNCH(RSVD_PHASE_BW_SMALL, 0.0, launch_tri_prep((const QrDesc*)dd(S.tri.off_desc), np, P.max_l, s));
+        PLAUNCH(RSVD_PHASE_BW_SMALL, 0.0,
+                launch_trsm_upper((const QrDesc*)dd(S.trsm.off_desc), (const int*)dd(S.trsm.off_begin), np,
+                                  S.trsm.total, P.max_l, s));
+        if ((rc = bgemm(S.da)) != RSVD_OK) return rc;
+        if ((rc = bgemm(S.qprev)) != RSVD_OK) return rc;
+    }
+    return RSVD_OK;
+}
+
+int plan_backward(rsvd_plan* P, const void* const* dU, const void* const* dS, const void* const* dVT,
+                  void* const* dA, double broad, hipStream_t stream, bool eager)
+{
+    if (!P) return fail(RSVD_ERR_INVALID, "plan is null");
+    if (P->fullsvd || !(P->flags & RSVD_PLAN_SAVE))
+        return fail(RSVD_ERR_INVALID, "backward needs an RSVD plan created with RSVD_PLAN_SAVE");
+    if (!P->fwd_saved) return fail(RSVD_ERR_INVALID, "backward needs a preceding rsvd_plan_execute");
+    if (!(broad >= 0.0) || !(broad < INFINITY)) return fail(RSVD_ERR_INVALID, "broadening must be finite and >= 0");
+    if (!dU || !dS || !dVT || !dA) return fail(RSVD_ERR_INVALID, "null cotangent or gradient array");
+    for (int b = 0; b < P->nprob; ++b) {
+        if (!dU[b] || !dS[b] || !dVT[b] || !dA[b]) return fail(RSVD_ERR_INVALID, "null matrix pointer in batch");
+        if (dA[b] == P->lastA[b]) return fail(RSVD_ERR_INVALID, "dA must not overlap A");
+    }
+    auto& W = P->bw;
+    bool same = W.valid && W.gen == P->fwd_gen && W.broad == broad;
+    for (int b = 0; b < P->nprob && same; ++b)
+        same = W.ldU[b] == dU[b] && W.ldS[b] == dS[b] && W.ldVT[b] == dVT[b] && W.ldA[b] == dA[b];
+    if (!same) {
+        if (W.upload_pending) HIPCHK(hipEventSynchronize(W.upload_done));
+        build_bw_blob(*P, dU, dS, dVT, dA, broad);
+        const size_t bytes = std::max<size_t>(W.hb.bytes.size(), 64);
+        if (W.dblob && bytes != W.bytes) return fail(RSVD_ERR_HIP, "descriptor layout changed");
+        if (!W.dblob) {
+            hipError_t e = hipMalloc(&W.dblob, bytes);
+            if (e == hipSuccess) e = hipHostMalloc(&W.hpinned, bytes, 0);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&W.upload_done, hipEventDisableTiming);
+            if (e != hipSuccess) return fail(RSVD_ERR_ALLOC, std::string("backward allocation: ") + hipGetErrorString(e));
+            W.bytes = bytes;
+        }
+        memcpy(W.hpinned, W.hb.bytes.data(), W.hb.bytes.size());
+        HIPCHK(hipMemcpyAsync(W.dblob, W.hpinned, W.hb.bytes.size(), hipMemcpyHostToDevice, stream));
+        HIPCHK(hipEventRecord(W.upload_done, stream));
+        W.upload_pending = true;
+        W.ldU.assign(dU, dU + P->nprob);
+        W.ldS.assign(dS, dS + P->nprob);
+        W.ldVT.assign(dVT, dVT + P->nprob);
+        W.ldA.assign(dA, dA + P->nprob);
+        W.broad = broad;
+        W.gen = P->fwd_gen;
+        W.valid = true;
+    }
+    if ((P->flags & RSVD_PLAN_GRAPH) && !eager) {
+        if (!W.gexec) {
+            HIPCHK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+            int rc = enqueue_backward(*P, P->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
+            if (rc != RSVD_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return fail(RSVD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+            W.graph = g;
+            HIPCHK(hipGraphInstantiate(&W.gexec, W.graph, nullptr, nullptr, 0));
+        }
+        HIPCHK(hipGraphLaunch(W.gexec, stream));
+        return RSVD_OK;
+    }
+    return enqueue_backward(*P, stream);
+}
+
 void plan_free(rsvd_plan* P)
 {
     if (!P) return;
@@ -659,6 +956,11 @@ void plan_free(rsvd_plan* P)
     if (P->ws) (void)hipFree(P->ws);
     if (P->dblob) (void)hipFree(P->dblob);
     if (P->hblob_pinned) (void)hipHostFree(P->hblob_pinned);
+    if (P->bw.gexec) (void)hipGraphExecDestroy(P->bw.gexec);
+    if (P->bw.graph) (void)hipGraphDestroy(P->bw.graph);
+    if (P->bw.upload_done) (void)hipEventDestroy(P->bw.upload_done);
+    if (P->bw.dblob) (void)hipFree(P->bw.dblob);
+    if (P->bw.hpinned) (void)hipHostFree(P->bw.hpinned);
     delete P;
 }
 
@@ -783,7 +1085,9 @@ int plan_execute(rsvd_plan* P, const void* const* A, void* const* U, void* const
         P->lastK = kk;
         P->lastInfo = info;
         P->blob_valid = true;
+        ++P->fwd_gen;
     }
+    P->fwd_saved = false;
     if (P->flags & RSVD_PLAN_GRAPH) {
         if (!P->gexec) {
             HIPCHK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -799,9 +1103,12 @@ int plan_execute(rsvd_plan* P, const void* const* A, void* const* U, void* const
             HIPCHK(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
         }
         HIPCHK(hipGraphLaunch(P->gexec, stream));
-        return RSVD_OK;
+    } else {
+        int rc = enqueue(*P, stream);
+        if (rc != RSVD_OK) return rc;
     }
-    return enqueue(*P, stream);
+    P->fwd_saved = (P->flags & RSVD_PLAN_SAVE) != 0 && !P->fullsvd;
+    return RSVD_OK;
 }
 
 // ---------------------------------------------------------------- one-shot cache
@@ -1009,6 +1316,45 @@ int rsvd_plan_profile(rsvd_plan_t* plan, const void* const* A, void* const* U, v
         for (const ProbHost& h : plan->probs) {
             HIPCHK(hipMemcpy(st.data(), plan->ws + h.o_stats, 2 * sizeof(int), hipMemcpyDeviceToHost));
             flops[RSVD_PHASE_JACOBI] += 2.0 * 32 * 32 * h.C * st[0] + 2.0 * 32 * 32 * ((double)h.C + h.R) * st[1];
+        }
+    }
+    return RSVD_OK;
+}
+
+int rsvd_plan_backward(rsvd_plan_t* plan, const void* const* dU, const void* const* dS, const void* const* dVT,
+                       void* const* dA, double broadening, void* stream)
+{
+    g_err.clear();
+    return plan_backward(plan, dU, dS, dVT, dA, broadening, (hipStream_t)stream, false);
+}
+
+int rsvd_plan_profile_backward(rsvd_plan_t* plan, const void* const* dU, const void* const* dS,
+                               const void* const* dVT, void* const* dA, double broadening, double* ms,
+                               int64_t* launches, double* flops, int ncat, void* stream)
+{
+    g_err.clear();
+    if (!plan || !ms || !launches || !flops || ncat < 1) return fail(RSVD_ERR_INVALID, "null profile output");
+    hipStream_t s = (hipStream_t)stream;
+    Profiler prof;
+    prof.s = s;
+    plan->prof = &prof;
+    int rc = plan_backward(plan, dU, dS, dVT, dA, broadening, s, true);
+    plan->prof = nullptr;
+    if (rc != RSVD_OK) return rc;
+    HIPCHK(hipStreamSynchronize(s));
+    for (int c = 0; c < ncat; ++c) {
+        ms[c] = 0.0;
+        launches[c] = 0;
+        flops[c] = 0.0;
+    }
+    for (size_t i = 0; i < prof.used; ++i) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, prof.ev[2 * i], prof.ev[2 * i + 1]));
+        const int c = prof.cat[i];
+        if (c < ncat) {
+            ms[c] += t;
+            launches[c] += 1;
+            flops[c] += prof.flops[i];
         }
     }
     return RSVD_OK;

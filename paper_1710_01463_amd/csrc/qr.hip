@@ -43,6 +43,47 @@ __device__ __forceinline__ double ld_elem(const void* p, int elem, int64_t i)
 // their current column.  Finally the 16 x 16 diagonal blocks of L are inverted
 // (one thread per column) into D, used by the substitution kernel.
 constexpr int PSTR = CHOL_W + 1;
+
+// Inverses of the 16 x 16 diagonal blocks of L (stored column-major: Rt[c * l
+// + r] = L[r][c]), D_I = L_II^-1 zero padded, for the substitution kernels.
+// The blocks are staged in LDS (lds: ceil(l/16) * 272 doubles) with their
+// reciprocal diagonals; each thread forms one column of one inverse by forward
+// substitution (branch free: the column is zero above its diagonal, so the
+// sums run over t < r).  Called by all NT threads of the block.
+template <int NT>
+__device__ void diag_block_inverses(const GLB double* __restrict__ Rt, int l, GLB double* __restrict__ Dg,
+                                    double* lds)
+{
+    const int tid = threadIdx.x;
+    const int nbk = (l + 15) / 16;
+    double* Pn = lds;
+    double* idg = lds + nbk * 256;
+    __syncthreads();
+    for (int e = tid; e < nbk * 256; e += NT) {
+        const int I = e / 256, i = (e / 16) % 16, j = e % 16;
+        const int gi = I * 16 + i, gj = I * 16 + j;
+        Pn[e] = (gi < l && gj < l && j <= i) ? Rt[(int64_t)gj * l + gi] : 0.0;
+    }
+    for (int e = tid; e < nbk * 16; e += NT) idg[e] = (e < l) ? 1.0 / Rt[(int64_t)e * l + e] : 0.0;
+    __syncthreads();
+    for (int e = tid; e < nbk * 16; e += NT) {
+        const int I = e / 16, c = e % 16;
+        const double* Lb = Pn + I * 256;
+        const double* ib = idg + I * 16;
+        double col[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            double s0 = 0.0;
+#pragma unroll
+            for (int t2 = 0; t2 < r; ++t2) s0 = fma(Lb[r * 16 + t2], col[t2], s0);
+            const double v = (r == c) ? ib[r] : -s0 * ib[r];
+            col[r] = (r < c) ? 0.0 : v;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Dg[(int64_t)I * 256 + r * 16 + c] = col[r];
+    }
+}
+
 // NT threads (one panel row each, NT >= l), a template parameter so that small
 // problems do not pay for the registers and barriers of large ones.
 template <int NT>
@@ -173,36 +214,7 @@ __global__ __launch_bounds__(NT) void chol_kernel(const QrDesc* __restrict__ des
         if (tid == 0) *to_glb(d.flag) = 1;
         return;
     }
-    // inverses of the diagonal blocks: D_I = L_II^-1 (16 x 16, zero padded).
-    // The blocks are staged in LDS with their reciprocal diagonals; each thread
-    // forms one column of one inverse by forward substitution (branch free:
-    // the column is zero above its diagonal, so the sums run over t < r).
-    const int nbk = (l + 15) / 16;
-    double* idg = Pn + nbk * 256;
-    for (int e = tid; e < nbk * 256; e += NT) {
-        const int I = e / 256, i = (e / 16) % 16, j = e % 16;
-        const int gi = I * 16 + i, gj = I * 16 + j;
-        Pn[e] = (gi < l && gj < l && j <= i) ? Rt[(int64_t)gj * l + gi] : 0.0;
-    }
-    for (int e = tid; e < nbk * 16; e += NT) idg[e] = (e < l) ? 1.0 / Rt[(int64_t)e * l + e] : 0.0;
-    __syncthreads();
-    GLB double* __restrict__ Dg = to_glb(d.D);
-    for (int e = tid; e < nbk * 16; e += NT) {
-        const int I = e / 16, c = e % 16;
-        const double* Lb = Pn + I * 256;
-        const double* ib = idg + I * 16;
-        double col[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            double s0 = 0.0;
-#pragma unroll
-            for (int t2 = 0; t2 < r; ++t2) s0 = fma(Lb[r * 16 + t2], col[t2], s0);
-            const double v = (r == c) ? ib[r] : -s0 * ib[r];
-            col[r] = (r < c) ? 0.0 : v;
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) Dg[(int64_t)I * 256 + r * 16 + c] = col[r];
-    }
+    diag_block_inverses<NT>(Rt, l, to_glb(d.D), Pn);
 }
 
 // ---------------------------------------------------------------- Q = M L^-T
@@ -289,6 +301,122 @@ __global__ __launch_bounds__(64) void trsm_kernel(const QrDesc* __restrict__ des
         const int r = e / l, c = e % l;
         Qout[(int64_t)(r0 + r) * l + c] = Qs[r * ldq + c];
     }
+}
+
+// ---------------------------------------------------------------- adjoint helpers
+// R (l x l, row-major) = Q^T M of a stage, computed by GEMM: zero its strictly
+// lower part so that it is exactly the upper-triangular factor, and form the
+// diagonal-block inverses of L = R^T for the substitution below.  (Row-major R
+// is the column-major storage of L.)
+__global__ __launch_bounds__(256) void tri_prep_kernel(const QrDesc* __restrict__ descs)
+{
+    extern __shared__ double lds[];
+    const QrDesc& d = descs[blockIdx.x];
+    if (d.Qout == nullptr) return;
+    const int l = d.l;
+    GLB double* __restrict__ R = to_glb(d.L);
+    for (int e = threadIdx.x; e < l * l; e += 256)
+        if (e / l > e % l) R[e] = 0.0;
+    diag_block_inverses<256>(R, l, to_glb(d.D), lds);
+}
+
+// Y = X L^-1 in place on the rows of X = Qout (rows x l), L lower triangular
+// stored column-major (Rt[c * l + r] = L[r][c]).  Row by row y L = x, i.e.
+// backward substitution: with Y^T = L^-T X^T, block column C of Y^T is
+// D_C^T (X^T[C] - L[>C, C]^T Y^T[>C]), C from the last block to the first;
+// both products are FP64 MFMA chains as in trsm_kernel.
+__global__ __launch_bounds__(64) void trsm_upper_kernel(const QrDesc* __restrict__ descs,
+                                                        const int* __restrict__ row_begin, int nprob)
+{
+    extern __shared__ double Qs[];  // 16 x (l + 1)
+    const int t = blockIdx.x;
+    const int b = find_problem(row_begin, nprob, t);
+    const QrDesc& d = descs[b];
+    if (d.Qout == nullptr) return;
+    const int l = d.l, rows = d.rows;
+    const int ldq = l + 1;
+    const int r0 = (t - row_begin[b]) * 16;
+    const int nr = min(16, rows - r0);
+    const GLB double* __restrict__ Rt = to_glb((const double*)d.L);
+    const GLB double* __restrict__ D = to_glb((const double*)d.D);
+    GLB double* __restrict__ Qout = to_glb(d.Qout);
+    const int lane = threadIdx.x;
+    const int l16 = lane & 15, lq = lane >> 4;
+
+    for (int base = lane; base < 16 * l; base += 64 * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = base + 64 * u;
+            const int r = e / l, c = e % l;
+            v[u] = (e < 16 * l && r < nr) ? Qout[(int64_t)(r0 + r) * l + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = base + 64 * u;
+            if (e < 16 * l) Qs[(e / l) * ldq + e % l] = v[u];
+        }
+    }
+    __syncthreads();
+    const int nbk = (l + 15) / 16;
+    for (int cb = nbk - 1; cb >= 0; --cb) {
+        const int C0 = cb * 16;
+        dbl4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = C0 + lq + 4 * r;
+            acc[r] = (c < l) ? Qs[l16 * ldq + c] : 0.0;
+        }
+        const int ci = C0 + l16;  // column of L supplying the A operand (A[i][k] = L[k][C0 + i])
+        for (int k0 = C0 + 16; k0 < l; k0 += 32) {
+            double av[8], bv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int kc = k0 + 4 * u + lq;
+                const bool ok = kc < l;
+                av[u] = (ok && ci < l) ? -Rt[(int64_t)ci * l + kc] : 0.0;
+                bv[u] = ok ? Qs[l16 * ldq + kc] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+        }
+        // res = D_C^T acc (A operand element (i, k) = D_C[k][i])
+        dbl4 res = {0, 0, 0, 0};
+        const GLB double* Dc = D + (int64_t)cb * 256;
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+            const double av = Dc[(4 * s2 + lq) * 16 + l16];
+            res = __builtin_amdgcn_mfma_f64_16x16x4f64(av, acc[s2], res, 0, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = C0 + lq + 4 * r;
+            if (c < l) Qs[l16 * ldq + c] = res[r];
+        }
+        __syncthreads();
+    }
+    for (int e = lane; e < nr * l; e += 64) {
+        const int r = e / l, c = e % l;
+        Qout[(int64_t)(r0 + r) * l + c] = Qs[r * ldq + c];
+    }
+}
+
+hipError_t launch_tri_prep(const QrDesc* d, int nprob, int max_l, hipStream_t s)
+{
+    if (nprob <= 0) return hipSuccess;
+    const size_t lds = (size_t)((max_l + 15) / 16) * 272 * sizeof(double);
+    hipLaunchKernelGGL(tri_prep_kernel, dim3(nprob), dim3(256), lds, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_trsm_upper(const QrDesc* d, const int* row_begin, int nprob, int total_blocks, int max_l,
+                             hipStream_t s)
+{
+    if (total_blocks <= 0) return hipSuccess;
+    const size_t lds = (size_t)16 * (max_l + 1) * sizeof(double);
+    hipLaunchKernelGGL(trsm_upper_kernel, dim3(total_blocks), dim3(64), lds, s, d, row_begin, nprob);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- Householder
@@ -411,6 +539,13 @@ hipError_t init_qr_kernels()
         e = hipFuncSetAttribute((const void*)chol_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize, chol_lds);
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void*)chol_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, chol_lds);
+    if (e != hipSuccess) return e;
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)trsm_upper_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                16 * (CHOL_MAX_L + 1) * (int)sizeof(double));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)tri_prep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (CHOL_MAX_L / 16) * 272 * (int)sizeof(double));
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)trsm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                16 * (CHOL_MAX_L + 1) * (int)sizeof(double));

@@ -166,6 +166,51 @@ class Plan:
                                           ms, nl, fl, nc, _stream()))
         return {name: (ms[i], int(nl[i]), fl[i]) for i, name in enumerate(L.PHASES)}
 
+    def _cotangent_ptrs(self, dU, dS, dVT, dA):
+        n = len(self.problems)
+        if not (len(dU) == len(dS) == len(dVT) == n):
+            raise ValueError("one cotangent triple per problem")
+        for i, pr in enumerate(self.problems):
+            U, S, VT = self.outputs[i]
+            for g, ref in ((dU[i], U), (dS[i], S), (dVT[i], VT)):
+                if g.shape != ref.shape or g.dtype != self.dtype or g.device.type != "cuda" or \
+                        not g.is_contiguous():
+                    raise ValueError("cotangent does not match its output (shape, dtype, contiguity)")
+        if dA is None:
+            dA = [torch.empty((pr["m"], pr.get("lda", pr["n"])), dtype=self.dtype, device=self.device)
+                  [:, :pr["n"]] for pr in self.problems]
+        if len(dA) != n:
+            raise ValueError("one gradient buffer per problem")
+        for g, pr in zip(dA, self.problems):
+            if g.shape != (pr["m"], pr["n"]) or g.dtype != self.dtype or g.device.type != "cuda" or \
+                    g.stride(1) != 1 or g.stride(0) != pr.get("lda", pr["n"]):
+                raise ValueError("dA must be row-major m x n with the plan's lda and dtype")
+        keep = (dU, dS, dVT, dA)
+        ptrs = tuple(L.ptr_array([t.data_ptr() for t in group]) for group in keep)
+        return ptrs, keep, dA
+
+    def backward(self, dU, dS, dVT, broadening=0.0, dA=None):
+        """Gradient over every A of <dU, U> + <dS, S> + <dVT, VT> for the most
+        recent execute (plan created with save=True).  Cotangents: lists of
+        contiguous tensors shaped like the outputs.  Returns the list of dA
+        (allocated unless given), without synchronising."""
+        ptrs, keep, dA = self._cotangent_ptrs(dU, dS, dVT, dA)
+        self._keep_bw = keep
+        L.check(L.lib().rsvd_plan_backward(self._h, *ptrs, float(broadening), _stream()))
+        return dA
+
+    def profile_backward(self, dU, dS, dVT, broadening=0.0, dA=None):
+        """The reverse pass without the graph, with HIP events around every
+        launch.  Returns {phase: (ms, launches, algorithmic_flops)}.  Blocking."""
+        ptrs, keep, dA = self._cotangent_ptrs(dU, dS, dVT, dA)
+        nc = len(L.PHASES)
+        ms = (ctypes.c_double * nc)()
+        nl = (ctypes.c_int64 * nc)()
+        fl = (ctypes.c_double * nc)()
+        L.check(L.lib().rsvd_plan_profile_backward(self._h, *ptrs, float(broadening), ms, nl, fl, nc,
+                                                   _stream()))
+        return {name: (ms[i], int(nl[i]), fl[i]) for i, name in enumerate(L.PHASES)}
+
     def close(self):
         if getattr(self, "_h", None):
             L.lib().rsvd_plan_destroy(self._h)
@@ -176,3 +221,61 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class RSVDFunction(torch.autograd.Function):
+    """Differentiable batched RSVD: forward runs a saving plan over the given
+    matrices, backward calls the library's hand-written adjoint with the
+    Gaussian test matrices held fixed (they depend on the seeds only).
+
+    apply(spec, *As) -> (U_0, S_0, VT_0, U_1, S_1, VT_1, ...), where spec is a
+    dict with keys k, p, q, seeds (one per matrix), delta, prec, broadening.
+    """
+
+    @staticmethod
+    def forward(ctx, spec, *As):
+        As = [_check_matrix(A) for A in As]
+        dtype = As[0].dtype
+        seeds = spec["seeds"]
+        probs = [dict(m=A.shape[0], n=A.shape[1], lda=A.stride(0), k=spec["k"], p=spec.get("p", 10),
+                      q=spec.get("q", 2), seed=int(seeds[i]), delta=spec.get("delta", 0.0))
+                 for i, A in enumerate(As)]
+        plan = Plan(probs, dtype, spec.get("prec", "f64"), graph=False, save=True, device=As[0].device)
+        plan.execute(As)
+        ctx.plan = plan
+        ctx.broadening = float(spec.get("broadening", 0.0))
+        ctx.shapes = [(A.shape, A.stride(0)) for A in As]
+        outs = []
+        for U, S, VT in plan.outputs:  # owned by this call's plan, never overwritten
+            outs += [U, S, VT]
+        return tuple(outs)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        plan = ctx.plan
+        nb = len(plan.problems)
+        dU, dS, dVT = [], [], []
+        for i in range(nb):
+            for lst, g, ref in ((dU, grads[3 * i], plan.outputs[i][0]), (dS, grads[3 * i + 1], plan.outputs[i][1]),
+                                (dVT, grads[3 * i + 2], plan.outputs[i][2])):
+                lst.append(torch.zeros_like(ref) if g is None else g.to(ref.dtype).contiguous())
+        dA = [torch.empty((shape[0], ld), dtype=plan.dtype, device=plan.device)[:, :shape[1]]
+              for shape, ld in ctx.shapes]
+        plan.backward(dU, dS, dVT, ctx.broadening, dA=dA)
+        ctx.plan = None
+        return (None,) + tuple(dA)
+
+
+def rsvd(A, k, p=10, q=2, seed=0, delta=0.0, prec="f64", broadening=0.0):
+    """Differentiable rank-k RSVD of one matrix: returns (U, S, VT)."""
+    return RSVDFunction.apply(dict(k=k, p=p, q=q, seeds=[seed], delta=delta, prec=prec,
+                                   broadening=broadening), A)
+
+
+def rsvd_batch(As, k, p=10, q=2, seeds=None, delta=0.0, prec="f64", broadening=0.0):
+    """Differentiable RSVD of a list of matrices (uniform k, p, q) in one plan:
+    returns a list of (U, S, VT) triples."""
+    seeds = list(range(len(As))) if seeds is None else list(seeds)
+    out = RSVDFunction.apply(dict(k=k, p=p, q=q, seeds=seeds, delta=delta, prec=prec,
+                                  broadening=broadening), *As)
+    return [tuple(out[3 * i:3 * i + 3]) for i in range(len(As))]

@@ -19,7 +19,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ["rsvd_truncate", "fullsvd_truncate", "rsvd_plan_create", "rsvd_plan_execute",
-              "rsvd_plan_destroy", "rsvd_last_error", "rsvd_plan_profile", "rsvd_gaussian"]:
+              "rsvd_plan_destroy", "rsvd_last_error", "rsvd_plan_profile", "rsvd_gaussian",
+              "rsvd_plan_backward", "rsvd_plan_profile_backward"]:
         assert n in names
 
 
@@ -67,6 +68,10 @@ def test_invalid_arguments_are_rejected_without_a_device():
     probs[0].m = probs[0].n = probs[0].lda = 4000
     assert lib.rsvd_plan_create(probs, 1, 0, 0, 0, ctypes.byref(h)) == _lib.RSVD_ERR_INVALID
     lib.rsvd_plan_destroy(None)
+    # backward without a plan
+    arr = (vp * 1)(16)
+    assert lib.rsvd_plan_backward(None, arr, arr, arr, arr, 0.0, None) == _lib.RSVD_ERR_INVALID
+    assert b"plan" in lib.rsvd_last_error()
 
 
 def test_python_layer_fails_loudly_without_the_library(monkeypatch):
