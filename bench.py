@@ -7,7 +7,8 @@ HBM before timing starts.  A step is one RSVD of every matrix of the batch.
 
 Also reported: the same-GPU full-SVD truncation (block one-sided Jacobi) on
 the same batch, the plain FP64 one-at-a-time RSVD, the accuracy of both at
-equal truncation error, and the CPU FP64 oracle on a bounded sample.
+equal truncation error, the CPU FP64 oracle on a bounded sample, and the
+differentiation workload (64 FP32 matrices 1024 x 1024, forward + adjoint).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f64|f32|bf16]
 """
@@ -31,6 +32,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the full-SVD and one-at-a-time legs")
     ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--no-diff", action="store_true", help="skip the forward + adjoint leg")
+    ap.add_argument("--diff-batch", type=int, default=64)
+    ap.add_argument("--diff-steps", type=int, default=5)
     return ap.parse_args()
 
 
@@ -65,6 +69,72 @@ def cpu_baseline(mats, probs, sample):
                       f"FP64 C oracle, one matrix per thread, {dt:.1f} s wall"}
 
 
+def gen_matrices(probs, dtype):
+    """Seeded test matrices, generated on the host in parallel (numpy releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(8) as ex:
+        return list(ex.map(lambda pr: pr.matrix().astype(dtype), probs))
+
+
+def diff_leg(args, P, torch, wl):
+    """Differentiation workload: 64 FP32 matrices 1024 x 1024, s_i = i^-1.5 with
+    three near-degenerate pairs, k = 128, p = 16, q = 2, FP32 sketch products;
+    one step = forward of the whole batch plus the hand-written adjoint for
+    seeded Gaussian cotangents (both HIP-graph launches)."""
+    import numpy as np
+    W = wl.c5(args.diff_batch)
+    probs = W.problems
+    log(f"[bench] differentiation leg: generating {len(probs)} matrices 1024x1024")
+    mats = gen_matrices(probs, np.float32)
+    As = [torch.from_numpy(A).cuda() for A in mats]
+    plist = [dict(m=pr.m, n=pr.n, k=pr.k, p=pr.p, q=pr.q, seed=pr.seed) for pr in probs]
+    plan = P.Plan(plist, torch.float32, "f32", graph=True, save=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1234)
+    dU = [torch.randn((pr.m, pr.k), generator=g, device="cuda") for pr in probs]
+    dS = [torch.randn((pr.k,), generator=g, device="cuda") for pr in probs]
+    dVT = [torch.randn((pr.k, pr.n), generator=g, device="cuda") for pr in probs]
+    dA = [torch.empty((pr.m, pr.n), device="cuda") for pr in probs]
+    for _ in range(2):
+        plan.execute(As)
+        plan.backward(dU, dS, dVT, 0.0, dA=dA)
+    torch.cuda.synchronize()
+    steps = args.diff_steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.execute(As)
+    torch.cuda.synchronize()
+    fms = (time.perf_counter() - t0) / steps * 1e3
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.execute(As)
+        plan.backward(dU, dS, dVT, 0.0, dA=dA)
+    torch.cuda.synchronize()
+    tms = (time.perf_counter() - t0) / steps * 1e3
+    info = plan.info.cpu().numpy()
+    finite = all(bool(torch.isfinite(x).all()) for x in dA)
+    bprof = plan.profile_backward(dU, dS, dVT, 0.0, dA=dA)
+    bw_gemm_ms, bw_gemm_n, bw_gemm_fl = bprof["bw_gemm"]
+    fprof = plan.profile(As)
+    fwd_fl = sum(v[2] for k, v in fprof.items() if k in ("sketch", "gram", "project", "backproj"))
+    plan.close()
+    return {
+        "workload": f"C5: {len(probs)} x 1024x1024 FP32, s_i=i^-1.5 with 3 pairs (gap 1e-6), "
+                    "k=128 p=16 q=2, FP32 sketch products, adjoint products FP64",
+        "forward_ms": fms,
+        "forward_backward_ms": tms,
+        "backward_ms": tms - fms,
+        "forward_backward_per_s": len(probs) / (tms / 1e3),
+        "status_ok": bool(np.all(info == 0)) and finite,
+        "bw_phases_ms": {k: round(v[0], 4) for k, v in bprof.items() if v[1] > 0},
+        "fw_phases_ms": {k: round(v[0], 4) for k, v in fprof.items() if v[1] > 0},
+        "bw_gemm_flops": bw_gemm_fl,
+        "fw_gemm_flops": fwd_fl,
+        "bw_gemm_tflops": bw_gemm_fl / (bw_gemm_ms * 1e-3) / 1e12 if bw_gemm_ms else None,
+        "bw_gemm_frac_of_fp64_peak": (bw_gemm_fl / (bw_gemm_ms * 1e-3) / 1e12) / 78.6 if bw_gemm_ms else None,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -81,7 +151,7 @@ def main():
     W = wl.c2(args.batch)
     probs = W.problems
     log(f"[bench] generating {len(probs)} matrices {probs[0].m}x{probs[0].n}")
-    mats = [pr.matrix() for pr in probs]
+    mats = gen_matrices(probs, np.float64)
     dtype = torch.float64 if args.prec == "f64" else torch.float32
     As = [torch.from_numpy(A).to(dtype).cuda() for A in mats]
     plist = [dict(m=pr.m, n=pr.n, k=pr.k, p=pr.p, q=pr.q, seed=pr.seed) for pr in probs]
@@ -181,6 +251,9 @@ def main():
             "eps_F_over_delta_EY_rsvd": eps_ratio,
             "eps_F_over_delta_EY_fullsvd": 1.0,
         }
+
+    if not args.no_diff:
+        result["differentiation"] = diff_leg(args, P, torch, wl)
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle leg")

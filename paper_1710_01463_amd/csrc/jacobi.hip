@@ -20,7 +20,8 @@ namespace rsvd {
 
 constexpr int JR = 2 * JAC_B;  // rows per block pair
 constexpr int JCH = 128;       // column chunk staged through LDS
-constexpr int JPF = JR * JCH / 256;  // prefetched doubles per thread
+constexpr int JT = 512;              // threads per workgroup
+constexpr int JPF = JR * JCH / JT;   // prefetched doubles per thread
 
 __device__ __forceinline__ int rr_block(int pos, int round, int nb)
 {
@@ -68,7 +69,7 @@ __device__ __forceinline__ void load_chunk(double (&pre)[JPF], const GLB double*
     const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < JPF; ++i) {
-        const int e = tid + 256 * i;
+        const int e = tid + JT * i;
         const int a = e / JCH, cc = e % JCH;
         const int gr = rowmap[a], gc = c0 + cc;
         pre[i] = (gr >= 0 && gc < ncols) ? M[(int64_t)gr * ldm + gc] : 0.0;
@@ -79,7 +80,7 @@ __device__ __forceinline__ void store_chunk(const double (&pre)[JPF], double (*X
     const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < JPF; ++i) {
-        const int e = tid + 256 * i;
+        const int e = tid + JT * i;
         Xs[e / JCH][e % JCH] = pre[i];
     }
 }
@@ -93,17 +94,11 @@ struct ChunkSeq {
     int C, R, ncx, nct;
     __device__ void select(int ci, GLB double*& M, int64_t& ldm, int& ncols, int& c0) const
     {
-        if (ci < ncx) {
-            M = X;
-            ldm = ldx;
-            ncols = C;
-            c0 = ci * JCH;
-        } else {
-            M = P;
-            ldm = ldp;
-            ncols = R;
-            c0 = (ci - ncx) * JCH;
-        }
+        const bool in_x = ci < ncx;
+        M = in_x ? X : P;
+        ldm = in_x ? ldx : ldp;
+        ncols = in_x ? C : R;
+        c0 = (in_x ? ci : ci - ncx) * JCH;
     }
     __device__ void load(double (&pre)[JPF], int ci, const int* rowmap) const
     {
@@ -132,7 +127,7 @@ __device__ void apply_rotation(const ChunkSeq& cs, double (&pre)[JPF], const int
         int ncols, c0;
         cs.select(ci, M, ldm, ncols, c0);
 #pragma unroll
-        for (int tj = wave; tj < JCH / 16; tj += 4) {
+        for (int tj = wave; tj < JCH / 16; tj += JT / 64) {
             dbl4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 #pragma unroll
             for (int kk = 0; kk < JR; kk += 4) {
@@ -156,7 +151,7 @@ __device__ void apply_rotation(const ChunkSeq& cs, double (&pre)[JPF], const int
 
 constexpr int JAC_INNER_SWEEPS = 1;
 
-__global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc* __restrict__ descs,
+__global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restrict__ descs,
                                                            const int* __restrict__ pair_begin, int nprob,
                                                            int sweep, int round)
 {
@@ -190,9 +185,11 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc* __rest
     if (tid == 0) any_rot = 0;
     __syncthreads();
 
-    // ---- Gram matrix of the 32 rows (FP64 MFMA), one 16 x 16 tile per wave
+    // ---- Gram matrix of the 32 rows (FP64 MFMA): wave w forms the 16 x 16
+    // tile (w / 2 % 2, w % 2) over one half of every column chunk; the two
+    // halves are added through LDS
     {
-        const int wi = wave >> 1, wj = wave & 1;
+        const int wi = (wave >> 1) & 1, wj = wave & 1, half = wave >> 2;
         dbl4 acc = {0, 0, 0, 0};
         double pre[JPF];
         load_chunk(pre, X, ldx, C, 0, rowmap);
@@ -201,15 +198,23 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc* __rest
             __syncthreads();
             if (c0 + JCH < C) load_chunk(pre, X, ldx, C, c0 + JCH, rowmap);
 #pragma unroll 8
-            for (int kk = 0; kk < JCH; kk += 4) {
+            for (int kk = half * (JCH / 2); kk < (half + 1) * (JCH / 2); kk += 4) {
                 const double av = Xs[wi * 16 + l16][kk + lq];
                 const double bv = Xs[wj * 16 + l16][kk + lq];
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
             }
             __syncthreads();
         }
+        if (half == 1) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Hbuf[0][wi * 16 + lq + 4 * r][wj * 16 + l16] = acc[r];
+            for (int r = 0; r < 4; ++r) Hbuf[1][wi * 16 + lq + 4 * r][wj * 16 + l16] = acc[r];
+        }
+        __syncthreads();
+        if (half == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                Hbuf[0][wi * 16 + lq + 4 * r][wj * 16 + l16] = acc[r] + Hbuf[1][wi * 16 + lq + 4 * r][wj * 16 + l16];
+        }
     }
     // prefetch the first chunk of the rotation phase; it lands during the inner solve
     ChunkSeq seq;
@@ -225,13 +230,13 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc* __rest
     seq.load(pre, 0, rowmap);
     __syncthreads();
     // symmetrise from the upper triangle, identity for P
-    for (int e = tid; e < JR * JR; e += 256) {
+    for (int e = tid; e < JR * JR; e += JT) {
         const int i = e / JR, j = e % JR;
         if (i > j) Hbuf[0][i][j] = Hbuf[0][j][i];
         Ps[i][j] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    for (int e = tid; e < JR * JR; e += 256) {
+    for (int e = tid; e < JR * JR; e += JT) {
         const int i = e / JR, j = e % JR;
         if (i < j) {
             const double a = Hbuf[0][i][i], c = Hbuf[0][j][j], g = Hbuf[0][i][j];
@@ -248,10 +253,13 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc* __rest
     if (tid == 0) rot[sweep] = 1;
 
     // ---- inner cyclic Jacobi on the 32 x 32 Gram matrix, parallel order.
-    // Thread (pi_, pj_) owns the 2 x 2 block (pair pi_ rows) x (pair pj_ cols)
-    // of H and the 2 x 2 block (pair pi_ rows) x (columns 2 pj_, 2 pj_ + 1) of
-    // P.  H is double-buffered so one barrier per step suffices.
-    const int pr_i = tid >> 4, pr_j = tid & 15;
+    // Thread t < 256, (pi_, pj_) = (t / 16, t % 16), owns the 2 x 2 block
+    // (pair pi_ rows) x (pair pj_ cols) of H; thread 256 + t owns the 2 x 2
+    // block (pair pi_ rows) x (columns 2 pj_, 2 pj_ + 1) of P, so the two
+    // updates run side by side.  H is double-buffered so one barrier per step
+    // suffices.
+    const bool on_h = tid < 256;
+    const int pr_i = (tid & 255) >> 4, pr_j = tid & 15;
     int cur = 0;
     for (int isw = 0; isw < JAC_INNER_SWEEPS; ++isw) {
         for (int step = 0; step < JR - 1; ++step) {
@@ -259,17 +267,19 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc* __rest
             const int p_j = rr_block(pr_j, step, JR), q_j = rr_block(JR - 1 - pr_j, step, JR);
             double (*H)[JR + 1] = Hbuf[cur];
             double (*Hn)[JR + 1] = Hbuf[cur ^ 1];
-            double ci, si, cj, sj;
+            double ci, si;
             jac_rotation(H[p_i][p_i], H[q_i][q_i], H[p_i][q_i], tol, ci, si);
-            jac_rotation(H[p_j][p_j], H[q_j][q_j], H[p_j][q_j], tol, cj, sj);
-            const double b00 = H[p_i][p_j], b01 = H[p_i][q_j], b10 = H[q_i][p_j], b11 = H[q_i][q_j];
-            const double t00 = ci * b00 - si * b10, t01 = ci * b01 - si * b11;
-            const double t10 = si * b00 + ci * b10, t11 = si * b01 + ci * b11;
-            Hn[p_i][p_j] = t00 * cj - t01 * sj;
-            Hn[p_i][q_j] = t00 * sj + t01 * cj;
-            Hn[q_i][p_j] = t10 * cj - t11 * sj;
-            Hn[q_i][q_j] = t10 * sj + t11 * cj;
-            if (si != 0.0) {
+            if (on_h) {
+                double cj, sj;
+                jac_rotation(H[p_j][p_j], H[q_j][q_j], H[p_j][q_j], tol, cj, sj);
+                const double b00 = H[p_i][p_j], b01 = H[p_i][q_j], b10 = H[q_i][p_j], b11 = H[q_i][q_j];
+                const double t00 = ci * b00 - si * b10, t01 = ci * b01 - si * b11;
+                const double t10 = si * b00 + ci * b10, t11 = si * b01 + ci * b11;
+                Hn[p_i][p_j] = t00 * cj - t01 * sj;
+                Hn[p_i][q_j] = t00 * sj + t01 * cj;
+                Hn[q_i][p_j] = t10 * cj - t11 * sj;
+                Hn[q_i][q_j] = t10 * sj + t11 * cj;
+            } else if (si != 0.0) {
                 const int c0 = 2 * pr_j, c1 = 2 * pr_j + 1;
                 const double x0 = Ps[p_i][c0], x1 = Ps[p_i][c1], y0 = Ps[q_i][c0], y1 = Ps[q_i][c1];
                 Ps[p_i][c0] = ci * x0 - si * y0;
@@ -290,7 +300,7 @@ hipError_t launch_jacobi_round(const JacDesc* d, const int* pair_begin, int npro
                                int sweep, int round, hipStream_t s)
 {
     if (total_pairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(jacobi_round_kernel, dim3(total_pairs), dim3(256), 0, s, d, pair_begin, nprob,
+    hipLaunchKernelGGL(jacobi_round_kernel, dim3(total_pairs), dim3(JT), 0, s, d, pair_begin, nprob,
                        sweep, round);
     return hipGetLastError();
 }
