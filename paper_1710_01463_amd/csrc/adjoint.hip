@@ -38,12 +38,13 @@ __global__ __launch_bounds__(256) void bw_prep_kernel(const BwDesc* __restrict__
                                                       const int* __restrict__ blk_begin, int nprob)
 {
     const int t = blockIdx.x;
-    const int b = find_problem(blk_begin, nprob, t);
+    const int2 wi_ = wg_item(blk_begin, t);
+    const int b = wi_.x;
     const BwDesc& d = descs[b];
     const int64_t m = d.m, n = d.n, l = d.l, k = d.k;
     const int64_t e1 = m * l, e2 = e1 + l * n, e3 = e2 + l * l, e4 = e3 + l;
     const GLB double* __restrict__ sgn = to_glb(d.sgn);
-    const int64_t base = (int64_t)(t - blk_begin[b]) * BW_ELEMS_PER_BLOCK + threadIdx.x;
+    const int64_t base = (int64_t)wi_.y * BW_ELEMS_PER_BLOCK + threadIdx.x;
 #pragma unroll
     for (int u = 0; u < BW_ELEMS_PER_BLOCK / 256; ++u) {
         const int64_t e = base + 256 * u;
@@ -94,14 +95,15 @@ __global__ __launch_bounds__(256) void bw_core_kernel(const BwDesc* __restrict__
                                                       const int* __restrict__ blk_begin, int nprob)
 {
     const int t = blockIdx.x;
-    const int b = find_problem(blk_begin, nprob, t);
+    const int2 wi_ = wg_item(blk_begin, t);
+    const int b = wi_.x;
     const BwDesc& d = descs[b];
     const int64_t n = d.n, l = d.l;
     const int64_t e1 = l * l, e2 = e1 + l * n;
     const GLB double* __restrict__ s = to_glb(d.sig);
     const double s1 = s[0];
     const double eps = d.broad * (s1 * s1) * (s1 * s1);
-    const int64_t base = (int64_t)(t - blk_begin[b]) * BW_ELEMS_PER_BLOCK + threadIdx.x;
+    const int64_t base = (int64_t)wi_.y * BW_ELEMS_PER_BLOCK + threadIdx.x;
 #pragma unroll
     for (int u = 0; u < BW_ELEMS_PER_BLOCK / 256; ++u) {
         const int64_t e = base + 256 * u;
@@ -134,10 +136,11 @@ __global__ __launch_bounds__(256) void bw_sym_kernel(const BwDesc* __restrict__ 
                                                      const int* __restrict__ blk_begin, int nprob)
 {
     const int t = blockIdx.x;
-    const int b = find_problem(blk_begin, nprob, t);
+    const int2 wi_ = wg_item(blk_begin, t);
+    const int b = wi_.x;
     const BwDesc& d = descs[b];
     const int64_t l = d.l;
-    const int64_t base = (int64_t)(t - blk_begin[b]) * BW_ELEMS_PER_BLOCK + threadIdx.x;
+    const int64_t base = (int64_t)wi_.y * BW_ELEMS_PER_BLOCK + threadIdx.x;
 #pragma unroll
     for (int u = 0; u < BW_ELEMS_PER_BLOCK / 256; ++u) {
         const int64_t e = base + 256 * u;

@@ -76,13 +76,11 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Binary search: index b with begin[b] <= t < begin[b+1], begin has nb+1 entries.
-__device__ __forceinline__ int find_problem(const int* __restrict__ begin, int nb, int t)
+// Work-item map of a batched launch: workgroup t serves problem map[t].x,
+// local item map[t].y (one load instead of a search over prefix sums, which
+// would put several dependent global loads at the start of every workgroup).
+__device__ __forceinline__ int2 wg_item(const int* __restrict__ map, int t)
 {
-    int lo = 0, hi = nb - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (begin[mid] <= t) lo = mid; else hi = mid - 1;
-    }
-    return lo;
+    const GLB int* m = to_glb(map) + 2 * (int64_t)t;
+    return make_int2(m[0], m[1]);
 }

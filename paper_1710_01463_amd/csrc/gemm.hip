@@ -62,10 +62,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
     __shared__ __attribute__((aligned(16))) OpT Xs[BN * LDK];
 
     const int t = blockIdx.x;
-    const int b = find_problem(tile_begin, nprob, t);
+    const int2 wi_ = wg_item(tile_begin, t);
+    const int b = wi_.x;
     const GemmDesc& d = descs[b];
     if (d.skip && *to_glb(d.skip)) return;
-    const int local = t - tile_begin[b];
+    const int local = wi_.y;
     const int m0 = (local / d.tiles_n) * BM;
     const int n0 = (local % d.tiles_n) * BN;
     const int M = d.M, N = d.N, K = d.K;

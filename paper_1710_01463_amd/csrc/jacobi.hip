@@ -28,7 +28,7 @@ __device__ __forceinline__ int rr_block(int pos, int round, int nb)
     return pos == 0 ? 0 : ((pos - 1 + round) % (nb - 1)) + 1;
 }
 
-// |g| > tol sqrt(a b), with a hardware square root (about 2^-22 relative):
+// |g| > tol sqrt(a b), with hardware square roots (about 2^-22 relative):
 // the threshold only decides whether a rotation is worth doing.
 __device__ __forceinline__ bool jac_needs(double a, double b, double g, double tol)
 {
@@ -38,28 +38,30 @@ __device__ __forceinline__ bool jac_needs(double a, double b, double g, double t
 // Rotation (c, s) that (nearly) zeroes the (p, q) entry of a symmetric 2 x 2
 // block [a g; g b] under x_p <- c x_p - s x_q, x_q <- s x_p + c x_q, from the
 // classical Hestenes/Jacobi formula t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
-// zeta = (b - a) / (2 g).  The angle may be approximate (hardware reciprocal
-// and square root): a slightly-off rotation leaves a tiny off-diagonal that
-// later rotations remove.  What must hold to working precision is c^2 + s^2 = 1,
-// so c = (1 + t^2)^(-1/2) is refined by two Newton steps.
+// zeta = (b - a) / (2 g) (scale free).  The angle may be approximate (hardware
+// reciprocal and square root): a slightly-off rotation leaves a tiny
+// off-diagonal that later rotations remove.  What must hold to working
+// precision is c^2 + s^2 = 1, so c = (1 + t^2)^(-1/2) is refined by two Newton
+// steps.  Everything is computed unconditionally and the identity selected
+// when no rotation is needed, so the threshold test is off the dependent
+// chain (each dependent FP64 operation costs tens of cycles).
 __device__ __forceinline__ void jac_rotation(double a, double b, double g, double tol, double& cs, double& sn)
 {
-    cs = 1.0;
-    sn = 0.0;
-    if (jac_needs(a, b, g, tol)) {
-        const double zeta = (b - a) * __builtin_amdgcn_rcp(2.0 * g);
-        double t;
-        if (fabs(zeta) > 1e150)
-            t = 0.5 * __builtin_amdgcn_rcp(zeta);
-        else
-            t = copysign(1.0, zeta) * __builtin_amdgcn_rcp(fabs(zeta) + __builtin_amdgcn_sqrt(fma(zeta, zeta, 1.0)));
-        const double x = fma(t, t, 1.0);
-        double y = __builtin_amdgcn_rsq(x);
-        y = y * fma(-0.5 * x * y, y, 1.5);
-        y = y * fma(-0.5 * x * y, y, 1.5);
-        cs = y;
-        sn = y * t;
+    const double zeta = (b - a) * __builtin_amdgcn_rcp(2.0 * g);
+    const double az = fabs(zeta);
+    const double tb = copysign(__builtin_amdgcn_rcp(az + __builtin_amdgcn_sqrt(fma(zeta, zeta, 1.0))), zeta);
+    const double t = (az > 1e150) ? 0.5 * __builtin_amdgcn_rcp(zeta) : tb;
+    const double x = fma(t, t, 1.0);
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double h = x * y;
+        const double e = fma(-h, y, 1.0);
+        y = fma(0.5 * y, e, y);
     }
+    const bool rot = jac_needs(a, b, g, tol);
+    cs = rot ? y : 1.0;
+    sn = rot ? y * t : 0.0;
 }
 
 // Loads the 32 x JCH chunk (rows via rowmap, columns c0..) of M into registers.
@@ -162,13 +164,14 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
     __shared__ int any_rot;
 
     const int t = blockIdx.x;
-    const int b = find_problem(pair_begin, nprob, t);
+    const int2 wi_ = wg_item(pair_begin, t);
+    const int b = wi_.x;
     const JacDesc& d = descs[b];
     const int nb = d.nb;
     if (round >= nb - 1) return;
     GLB int* __restrict__ rot = to_glb(d.rot);
     if (sweep > 0 && rot[sweep - 1] == 0) return;
-    const int pi = t - pair_begin[b];
+    const int pi = wi_.y;
     const int I = rr_block(pi, round, nb);
     const int J = rr_block(nb - 1 - pi, round, nb);
     const int R = d.R, C = d.C;
@@ -490,9 +493,10 @@ __global__ __launch_bounds__(64) void signfix_kernel(const FinDesc* __restrict__
                                                      const int* __restrict__ col_begin, int nprob)
 {
     const int t = blockIdx.x;
-    const int b = find_problem(col_begin, nprob, t);
+    const int2 wi_ = wg_item(col_begin, t);
+    const int b = wi_.x;
     const FinDesc& d = descs[b];
-    const int j = t - col_begin[b];
+    const int j = wi_.y;
     const int lane = threadIdx.x;
     const int64_t kk = *to_glb(d.kkept_out);
     GLB TO* __restrict__ U = (GLB TO*)d.U;

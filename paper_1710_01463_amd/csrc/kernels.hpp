@@ -36,8 +36,10 @@ enum Elem : int { E_F64 = 0, E_F32 = 1, E_BF16 = 2 };
 constexpr int GEMM_BM = 64;
 constexpr int GEMM_BN = 64;
 
-// descs: device array of nprob descriptors; tile_begin: device array of nprob+1 prefix
-// sums of per-problem tile counts (ceil(M/64) * ceil(N/64)).
+// descs: device array of nprob descriptors; tile_begin: the launch's work-item map,
+// total_tiles int pairs (problem, tile index), a problem with ceil(M/64) * ceil(N/64)
+// tiles contributing that many consecutive entries.  Every "*_begin" argument of
+// the launchers below is such a map over that launch's items.
 hipError_t launch_gemm(GemmKind kind, Elem ea, Elem ex, Elem ec, const GemmDesc* descs,
                        const int* tile_begin, int nprob, int total_tiles, hipStream_t stream);
 
@@ -63,7 +65,7 @@ struct QrDesc {
 constexpr int CHOL_MAX_L = 1024;
 hipError_t launch_chol(const QrDesc* d, int nprob, int max_l, hipStream_t s);
 // Qout = src L^-T, src = Min (from_min = 1) or Qout (from_min = 0, in place);
-// row_begin: prefix sums of ceil(rows / 16).
+// row_begin: item map over the ceil(rows / 16) row blocks of every problem.
 hipError_t launch_trsm(const QrDesc* d, const int* row_begin, int nprob, int total_blocks, int from_min,
                        int max_l, hipStream_t s);
 // Raises the dynamic-LDS limit of the Cholesky kernel.
@@ -124,7 +126,7 @@ struct FinDesc {
 };
 hipError_t launch_finish(const FinDesc* d, int nprob, int out_f64, hipStream_t s);
 // Zero columns >= k_kept of U and make the largest-magnitude entry of every kept
-// left vector positive (flipping the matching row of VT).  col_begin: prefix of k.
+// left vector positive (flipping the matching row of VT).  col_begin: item map over k columns.
 hipError_t launch_signfix(const FinDesc* d, const int* col_begin, int nprob, int total_cols,
                           int out_f64, hipStream_t s);
 
@@ -208,7 +210,7 @@ struct BwDesc {
     int pad_;
     double broad;       // Lorentzian broadening eps = broad * sigma_1^4
 };
-// blk_begin: prefix sums of per-problem block counts, ceil(bw_*_elems / BW_ELEMS_PER_BLOCK).
+// blk_begin: item map over ceil(bw_*_elems / BW_ELEMS_PER_BLOCK) blocks per problem.
 int64_t bw_prep_elems(int m, int n, int l);
 int64_t bw_core_elems(int n, int l);
 int64_t bw_sym_elems(int l);

@@ -307,15 +307,31 @@ template <typename T> T* wsp(const rsvd_plan& P, size_t off) { return (T*)(P.ws 
 
 int tiles_of(int M, int N) { return ((M + GEMM_BM - 1) / GEMM_BM) * ((N + GEMM_BN - 1) / GEMM_BN); }
 
+// Work-item map of a batched launch: entry t = (problem, local item) for
+// workgroup t, problems in order, count[b] items each.
+std::vector<int> item_map(const std::vector<int>& counts)
+{
+    std::vector<int> map;
+    for (size_t b = 0; b < counts.size(); ++b)
+        for (int i = 0; i < counts[b]; ++i) {
+            map.push_back((int)b);
+            map.push_back(i);
+        }
+    if (map.empty()) map.assign(2, 0);
+    return map;
+}
+
 GemmLaunch add_gemm(Blob& B, GemmKind kind, Elem ea, Elem ex, Elem ec, std::vector<GemmDesc>& descs)
 {
-    std::vector<int> begin(descs.size() + 1, 0);
+    std::vector<int> counts(descs.size(), 0);
+    int total = 0;
     for (size_t b = 0; b < descs.size(); ++b) {
         GemmDesc& d = descs[b];
         int t = 0;
         if (d.M > 0 && d.N > 0 && d.K >= 0 && d.A != nullptr) t = tiles_of(d.M, d.N);
         d.tiles_n = (d.N + GEMM_BN - 1) / GEMM_BN;
-        begin[b + 1] = begin[b] + t;
+        counts[b] = t;
+        total += t;
     }
     GemmLaunch g;
     g.kind = kind;
@@ -323,8 +339,8 @@ GemmLaunch add_gemm(Blob& B, GemmKind kind, Elem ea, Elem ex, Elem ec, std::vect
     g.ex = ex;
     g.ec = ec;
     g.off_desc = B.add(descs);
-    g.off_begin = B.add(begin);
-    g.total = begin.back();
+    g.off_begin = B.add(item_map(counts));
+    g.total = total;
     g.flops = 0.0;
     for (const GemmDesc& d : descs)
         if (d.A != nullptr) g.flops += 2.0 * d.M * d.N * d.K;
@@ -333,12 +349,11 @@ GemmLaunch add_gemm(Blob& B, GemmKind kind, Elem ea, Elem ex, Elem ec, std::vect
 
 template <typename D> IdxLaunch add_idx(Blob& B, const std::vector<D>& descs, const std::vector<int>& counts)
 {
-    std::vector<int> begin(counts.size() + 1, 0);
-    for (size_t b = 0; b < counts.size(); ++b) begin[b + 1] = begin[b] + counts[b];
     IdxLaunch L;
     L.off_desc = B.add(descs);
-    L.off_begin = B.add(begin);
-    L.total = begin.back();
+    L.off_begin = B.add(item_map(counts));
+    L.total = 0;
+    for (int c : counts) L.total += c;
     return L;
 }
 
@@ -1251,15 +1266,16 @@ int rsvd_gaussian(uint64_t seed, int64_t n, int64_t l, double* omega, void* stre
     d.l = (int)l;
     d.elem = E_F64;
     const int64_t pairs = (n + 1) / 2 * l;
-    std::vector<int> begin = {0, (int)((pairs + 255) / 256)};
+    const int nblk = (int)((pairs + 255) / 256);
+    const std::vector<int> map = item_map(std::vector<int>(1, nblk));
     hipStream_t s = (hipStream_t)stream;
     OmegaDesc* dd = nullptr;
     int* db = nullptr;
     HIPCHK(hipMalloc(&dd, sizeof(d)));
-    hipError_t e = hipMalloc(&db, sizeof(int) * 2);
+    hipError_t e = hipMalloc(&db, sizeof(int) * map.size());
     if (e == hipSuccess) e = hipMemcpyAsync(dd, &d, sizeof(d), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(db, begin.data(), sizeof(int) * 2, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_omega(dd, db, 1, begin[1], s);
+    if (e == hipSuccess) e = hipMemcpyAsync(db, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_omega(dd, db, 1, nblk, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(dd);
     if (db) (void)hipFree(db);

@@ -33,9 +33,10 @@ __global__ __launch_bounds__(256) void stage_kernel(const StageDesc* __restrict_
 {
     __shared__ double red[4];
     const int t = blockIdx.x;
-    const int b = find_problem(chunk_begin, nprob, t);
+    const int2 wi_ = wg_item(chunk_begin, t);
+    const int b = wi_.x;
     const StageDesc& d = descs[b];
-    const int c = t - chunk_begin[b];
+    const int c = wi_.y;
     const int r0 = c * STAGE_ROWS;
     const int nr = min(STAGE_ROWS, d.m - r0);
     const int n = d.n;
@@ -96,9 +97,10 @@ __global__ __launch_bounds__(256) void omega_kernel(const OmegaDesc* __restrict_
                                                     const int* __restrict__ blk_begin, int nprob)
 {
     const int t = blockIdx.x;
-    const int b = find_problem(blk_begin, nprob, t);
+    const int2 wi_ = wg_item(blk_begin, t);
+    const int b = wi_.x;
     const OmegaDesc& d = descs[b];
-    const int64_t idx = (int64_t)(t - blk_begin[b]) * 256 + threadIdx.x;
+    const int64_t idx = (int64_t)wi_.y * 256 + threadIdx.x;
     const int l = d.l, n = d.n;
     const int64_t pairs = (int64_t)((n + 1) / 2) * l;
     if (idx >= pairs) return;
@@ -155,9 +157,10 @@ __global__ __launch_bounds__(256) void copy_f64_kernel(const CopyDesc* __restric
 {
     __shared__ double T[64][65];
     const int t = blockIdx.x;
-    const int b = find_problem(blk_begin, nprob, t);
+    const int2 wi_ = wg_item(blk_begin, t);
+    const int b = wi_.x;
     const CopyDesc& d = descs[b];
-    const int local = t - blk_begin[b];
+    const int local = wi_.y;
     const int tn = (d.n + 63) / 64;
     const int i0 = (local / tn) * 64, j0 = (local % tn) * 64;
     const int tid = threadIdx.x;
@@ -191,9 +194,10 @@ __global__ __launch_bounds__(256) void eye_kernel(const EyeDesc* __restrict__ de
                                                   const int* __restrict__ blk_begin, int nprob)
 {
     const int t = blockIdx.x;
-    const int b = find_problem(blk_begin, nprob, t);
+    const int2 wi_ = wg_item(blk_begin, t);
+    const int b = wi_.x;
     const EyeDesc& d = descs[b];
-    const int64_t idx = (int64_t)(t - blk_begin[b]) * 256 + threadIdx.x;
+    const int64_t idx = (int64_t)wi_.y * 256 + threadIdx.x;
     const int64_t R = d.R;
     if (idx >= R * R) return;
     const int64_t i = idx / R, j = idx % R;

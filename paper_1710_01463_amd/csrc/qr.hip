@@ -14,7 +14,6 @@
 
 namespace rsvd {
 
-constexpr int CHOL_W = 16;
 // A pivot d_j of the Cholesky factorisation equals ||m_j||^2 sin^2 of the angle
 // between column j and the previous columns; below this fraction of ||m_j||^2
 // the factor no longer yields an orthonormal Q and Householder takes over.
@@ -30,19 +29,6 @@ __device__ __forceinline__ double ld_elem(const void* p, int elem, int64_t i)
     if (elem == E_F32) return ld_any<float>(p, i);
     return ld_any<__bf16>(p, i);
 }
-
-// ---------------------------------------------------------------- Cholesky
-// One workgroup per problem: G (l x l, FP64) = L L^T, left-looking by
-// 16-column panels.  The factor is stored column-major (the buffer holds
-// R = L^T row-major), so that the MFMA operands L[row][k] for 16 consecutive
-// rows are contiguous.  Each thread keeps its panel rows (up to 4) in
-// registers; the update with the already factored columns,
-// P -= L[J:, :J] L[J:J+16, :J]^T, is an FP64 MFMA product per 16-row tile
-// exchanged through LDS; the panel is then factored in registers with one
-// barrier per column, in which the 16 rows of the diagonal block publish
-// their current column.  Finally the 16 x 16 diagonal blocks of L are inverted
-// (one thread per column) into D, used by the substitution kernel.
-constexpr int PSTR = CHOL_W + 1;
 
 // Inverses of the 16 x 16 diagonal blocks of L (stored column-major: Rt[c * l
 // + r] = L[r][c]), D_I = L_II^-1 zero padded, for the substitution kernels.
@@ -84,137 +70,193 @@ __device__ void diag_block_inverses(const GLB double* __restrict__ Rt, int l, GL
     }
 }
 
-// NT threads (one panel row each, NT >= l), a template parameter so that small
-// problems do not pay for the registers and barriers of large ones.
-template <int NT>
-__global__ __launch_bounds__(NT) void chol_kernel(const QrDesc* __restrict__ descs)
+// ---------------------------------------------------------------- right-looking Cholesky
+__device__ __forceinline__ double readlane_f64(double v, int src)
 {
-    constexpr int CH_ROWS = 1;
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, src);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), src);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// 1 / sqrt(x) to working precision: hardware estimate and two Newton steps
+// (each written as three dependent operations).
+__device__ __forceinline__ double rsqrt_f64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double h = x * y;
+        const double e = fma(-h, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+// One workgroup per problem: G (l x l, FP64, lower triangle used) = L L^T,
+// right-looking by 16-column panels, the trailing matrix updated in place in
+// G.  Per panel: (1) one wave factors the 16 x 16 diagonal block in registers
+// (lane r holds row r; the column entries travel by readlane, so the 16
+// sequential column steps need no barrier or LDS round trip) and inverts it
+// by column-oriented substitution; (2) the panel below, L_iJ = G_iJ L_JJ^-T,
+// is formed by FP64 MFMA tiles into d.L and into LDS; (3) the trailing
+// update G_IK -= L_IJ L_KJ^T (lower tiles only) takes its MFMA operands from
+// the LDS copy of the panel, each wave loading the G tiles of a group of
+// tiles before multiplying them, so that memory latency is paid once per
+// group.  Three barriers per panel.  A pivot that falls below CHOL_PIVOT_REL
+// times the original diagonal entry sets the breakdown flag.  Writes L
+// column-major into d.L and the diagonal-block inverses into d.D.
+constexpr int CHOL_GRP = 4;  // trailing tiles per wave and load group
+
+template <int NT>
+__global__ __launch_bounds__(NT) void chol_rl_kernel(const QrDesc* __restrict__ descs)
+{
     constexpr int NW = NT / 64;
-    extern __shared__ double Pn[];  // rows x PSTR update terms, later the diagonal blocks
-    __shared__ double pub[2][CHOL_W];
-    __shared__ double gdiag[CHOL_W];
-    __shared__ double sqs[CHOL_W];  // 1 / sqrt(pivot) of the panel columns
+    extern __shared__ double dyn[];  // g0 (l), then the panel copy Lp (16 ceil((l - J - 16) / 16) < l rows x 17)
+    __shared__ double Lb[16][17];
+    __shared__ double Li[16][17];
+    __shared__ double idg[16];
+    __shared__ int bad_s;
     const QrDesc& d = descs[blockIdx.x];
     if (d.Qout == nullptr || *to_glb(d.flag)) return;
     const int l = d.l;
-    const GLB double* __restrict__ G = to_glb((const double*)d.G);
+    double* g0 = dyn;
+    double(*Lp)[17] = reinterpret_cast<double(*)[17]>(dyn + ((l + 1) & ~1));
+    GLB double* __restrict__ G = to_glb(d.G);
     GLB double* __restrict__ Rt = to_glb(d.L);  // Rt[c * l + r] = L[r][c]
+    GLB double* __restrict__ Dg = to_glb(d.D);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
-    bool bad = false;
+    for (int i = tid; i < l; i += NT) g0[i] = G[(int64_t)i * l + i];
+    if (tid == 0) bad_s = 0;
+    __syncthreads();
 
-    for (int J = 0; J < l; J += CHOL_W) {
-        const int w = min(CHOL_W, l - J);
-        const int rows = l - J;
-        if (tid < CHOL_W) gdiag[tid] = (tid < w) ? G[(int64_t)(J + tid) * l + J + tid] : 1.0;
-        // update terms with the factored columns 0..J-1 (MFMA), into LDS
-        if (J > 0) {
-            const int nt = (rows + 15) / 16;
-            const int rb = J + l16;  // B operand row (panel column l16)
-            for (int tb = 0; tb < nt; tb += 4 * NW) {
-                dbl4 acc[4];
+    for (int J = 0; J < l; J += 16) {
+        const int w = min(16, l - J);
+        // (1) diagonal block: factor and invert in wave 0
+        if (wave == 0) {
+            const int r = l16;
+            double a[16];
 #pragma unroll
-                for (int tt = 0; tt < 4; ++tt) acc[tt] = dbl4{0, 0, 0, 0};
-                for (int k0 = 0; k0 < J; k0 += 16) {
-                    double bv[4], av[4][4];
+            for (int c = 0; c < 16; ++c)
+                a[c] = (r < w && c < w && c <= r) ? G[(int64_t)(J + r) * l + J + c] : (r == c ? 1.0 : 0.0);
+            bool bad = false;
+            double dinv = 1.0;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int kc = k0 + 4 * u + lq;
-                        bv[u] = (l16 < w) ? Rt[(int64_t)kc * l + rb] : 0.0;
-                    }
+            for (int c = 0; c < 16; ++c) {
+                const double pc = readlane_f64(a[c], c);
+                const double gref = (c < w) ? g0[J + c] : 1.0;
+                bad = bad || !(pc > CHOL_PIVOT_REL * gref) || !(pc < INFINITY);
+                const double inv = rsqrt_f64(pc);
+                const double lrc = (r == c) ? pc * inv : a[c] * inv;
+                a[c] = lrc;
+                if (r == c) dinv = inv;
 #pragma unroll
-                    for (int tt = 0; tt < 4; ++tt) {
-                        const int ti = tb + wave + NW * tt;
-                        const int ra = J + ti * 16 + l16;
+                for (int k = c + 1; k < 16; ++k) {
+                    const double lkc = readlane_f64(lrc, k);
+                    if (r >= k) a[k] = fma(-lrc, lkc, a[k]);
+                }
+            }
+            if (lane < 16) {
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int kc = k0 + 4 * u + lq;
-                            av[tt][u] = (ti < nt && ra < l) ? Rt[(int64_t)kc * l + ra] : 0.0;
-                        }
-                    }
+                for (int c = 0; c < 16; ++c) Lb[r][c] = (c <= r) ? a[c] : 0.0;
+                idg[r] = dinv;
+            }
+            if (lane == 0) bad_s = bad ? 1 : 0;
+            // inverse, column c = lane: x_t = s_t / L_tt, then s_r -= L_rt x_t (r > t)
+            if (lane < 16) {
+                const int c = lane;
+                double sv[16], col[16];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
+                for (int rr = 0; rr < 16; ++rr) sv[rr] = (rr == c) ? 1.0 : 0.0;
 #pragma unroll
-                        for (int tt = 0; tt < 4; ++tt)
-                            acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[tt][u], bv[u], acc[tt], 0, 0, 0);
+                for (int t2 = 0; t2 < 16; ++t2) {
+                    col[t2] = (t2 < c) ? 0.0 : sv[t2] * idg[t2];
+#pragma unroll
+                    for (int rr = t2 + 1; rr < 16; ++rr) sv[rr] = fma(-Lb[rr][t2], col[t2], sv[rr]);
                 }
 #pragma unroll
-                for (int tt = 0; tt < 4; ++tt) {
-                    const int ti = tb + wave + NW * tt;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = ti * 16 + lq + 4 * r;
-                        if (ti < nt && i < rows) Pn[i * PSTR + l16] = acc[tt][r];
-                    }
+                for (int rr = 0; rr < 16; ++rr) {
+                    Li[rr][c] = col[rr];
+                    Dg[(int64_t)(J / 16) * 256 + rr * 16 + c] = (rr < w && c < w) ? col[rr] : 0.0;
                 }
             }
         }
         __syncthreads();
-        // panel rows of this thread, read column-wise from the symmetric G (coalesced)
-        double row[CH_ROWS][CHOL_W];
-#pragma unroll
-        for (int i = 0; i < CH_ROWS; ++i) {
-            const int r = tid + NT * i;
-#pragma unroll
-            for (int c = 0; c < CHOL_W; ++c)
-                row[i][c] = (r < rows && c < w && c <= r) ? G[(int64_t)(J + c) * l + J + r] : 0.0;
+        if (bad_s) {
+            if (tid == 0) *to_glb(d.flag) = 1;
+            return;
         }
-        if (J > 0) {
+        for (int e = tid; e < 256; e += NT) {
+            const int r = e >> 4, c = e & 15;
+            if (r < w && c < w) Rt[(int64_t)(J + c) * l + J + r] = (c <= r) ? Lb[r][c] : 0.0;
+        }
+        // (2) panel below the diagonal block: L_iJ = G_iJ L_JJ^-T (row i - J - 16 of Lp)
+        const int nrt = (l - J - 16 + 15) / 16;
+        for (int t = wave; t < nrt; t += NW) {
+            const int I0 = J + 16 + 16 * t;
+            double av[4];
 #pragma unroll
-            for (int i = 0; i < CH_ROWS; ++i) {
-                const int r = tid + NT * i;
-                if (r < rows) {
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int k = 4 * s4 + lq;
+                av[s4] = (I0 + l16 < l && k < w) ? G[(int64_t)(I0 + l16) * l + J + k] : 0.0;
+            }
+            dbl4 acc = {0, 0, 0, 0};
 #pragma unroll
-                    for (int c = 0; c < CHOL_W; ++c) row[i][c] -= Pn[r * PSTR + c];
-                }
+            for (int s4 = 0; s4 < 4; ++s4)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], Li[l16][4 * s4 + lq], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = I0 + lq + 4 * r;
+                const double v = (i < l && l16 < w) ? acc[r] : 0.0;
+                Lp[16 * t + lq + 4 * r][l16] = v;
+                if (i < l && l16 < w) Rt[(int64_t)(J + l16) * l + i] = v;
             }
         }
-        // factor the panel in registers: column c's pivot is the current
-        // L'[c][c]; rows below lose l_rc l_cc' (scaling deferred to the end)
+        __syncthreads();
+        // (3) trailing update of the lower tiles: G_IK -= L_IJ L_KJ^T
+        const int ntile = nrt * (nrt + 1) / 2;
+        for (int t0 = wave * CHOL_GRP; t0 < ntile; t0 += NW * CHOL_GRP) {
+            int ti[CHOL_GRP], tk[CHOL_GRP];
+            dbl4 acc[CHOL_GRP];
 #pragma unroll
-        for (int c = 0; c < CHOL_W; ++c) {
-            if (c < w && !bad) {
-                double* pb = pub[c & 1];
-                if (tid >= c && tid < w) pb[tid] = row[0][c];
-                __syncthreads();
-                const double dc = pb[c];
-                if (!(dc > CHOL_PIVOT_REL * gdiag[c]) || !(dc < INFINITY)) {
-                    bad = true;  // uniform: every thread read the same value
-                } else {
-                    const double inv = 1.0 / dc;
-                    if (tid == 0) sqs[c] = 1.0 / sqrt(dc);
+            for (int g = 0; g < CHOL_GRP; ++g) {
+                const int t = t0 + g;
+                int a = 0, rem = (t < ntile) ? t : 0;
+                while (rem > a) {
+                    rem -= a + 1;
+                    ++a;
+                }
+                ti[g] = (t < ntile) ? a : -1;
+                tk[g] = rem;
 #pragma unroll
-                    for (int i = 0; i < CH_ROWS; ++i) {
-                        const int r = tid + NT * i;
-                        if (r > c && r < rows) {
-                            const double f = row[i][c] * inv;
-#pragma unroll
-                            for (int cc = c + 1; cc < CHOL_W; ++cc)
-                                if (cc < w && (r >= CHOL_W || cc <= r)) row[i][cc] -= f * pb[cc];
-                        }
-                    }
+                for (int r = 0; r < 4; ++r) {
+                    const int i = J + 16 + 16 * a + lq + 4 * r, j = J + 16 + 16 * rem + l16;
+                    acc[g][r] = (t < ntile && i < l && j < l) ? G[(int64_t)i * l + j] : 0.0;
                 }
             }
-        }
-        if (bad) break;
-        __syncthreads();  // sqs complete
 #pragma unroll
-        for (int i = 0; i < CH_ROWS; ++i) {
-            const int r = tid + NT * i;
-            if (r < rows) {
+            for (int g = 0; g < CHOL_GRP; ++g) {
+                if (ti[g] < 0) continue;
 #pragma unroll
-                for (int c = 0; c < CHOL_W; ++c)
-                    if (c < w) Rt[(int64_t)(J + c) * l + J + r] = (c <= r) ? row[i][c] * sqs[c] : 0.0;
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    const int k = 4 * s4 + lq;
+                    acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(-Lp[16 * ti[g] + l16][k], Lp[16 * tk[g] + l16][k],
+                                                                  acc[g], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < CHOL_GRP; ++g) {
+                if (ti[g] < 0) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = J + 16 + 16 * ti[g] + lq + 4 * r, j = J + 16 + 16 * tk[g] + l16;
+                    if (i < l && j < l) G[(int64_t)i * l + j] = acc[g][r];
+                }
             }
         }
         __syncthreads();
     }
-    if (bad) {
-        if (tid == 0) *to_glb(d.flag) = 1;
-        return;
-    }
-    diag_block_inverses<NT>(Rt, l, to_glb(d.D), Pn);
 }
 
 // ---------------------------------------------------------------- Q = M L^-T
@@ -227,12 +269,13 @@ __global__ __launch_bounds__(64) void trsm_kernel(const QrDesc* __restrict__ des
 {
     extern __shared__ double Qs[];  // 16 x (l + 1)
     const int t = blockIdx.x;
-    const int b = find_problem(row_begin, nprob, t);
+    const int2 wi_ = wg_item(row_begin, t);
+    const int b = wi_.x;
     const QrDesc& d = descs[b];
     if (d.Qout == nullptr || *to_glb(d.flag)) return;
     const int l = d.l, rows = d.rows;
     const int ldq = l + 1;
-    const int r0 = (t - row_begin[b]) * 16;
+    const int r0 = wi_.y * 16;
     const int nr = min(16, rows - r0);
     const GLB double* __restrict__ Rt = to_glb((const double*)d.L);  // Rt[k * l + r] = L[r][k]
     const GLB double* __restrict__ D = to_glb((const double*)d.D);
@@ -330,12 +373,13 @@ __global__ __launch_bounds__(64) void trsm_upper_kernel(const QrDesc* __restrict
 {
     extern __shared__ double Qs[];  // 16 x (l + 1)
     const int t = blockIdx.x;
-    const int b = find_problem(row_begin, nprob, t);
+    const int2 wi_ = wg_item(row_begin, t);
+    const int b = wi_.x;
     const QrDesc& d = descs[b];
     if (d.Qout == nullptr) return;
     const int l = d.l, rows = d.rows;
     const int ldq = l + 1;
-    const int r0 = (t - row_begin[b]) * 16;
+    const int r0 = wi_.y * 16;
     const int nr = min(16, rows - r0);
     const GLB double* __restrict__ Rt = to_glb((const double*)d.L);
     const GLB double* __restrict__ D = to_glb((const double*)d.D);
@@ -507,18 +551,19 @@ __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restri
     }
 }
 
+static size_t chol_lds_bytes(int max_l)
+{
+    return (size_t)(((max_l + 1) & ~1) + (size_t)max_l * 17) * sizeof(double);  // g0, then Lp rows < l
+}
+
 hipError_t launch_chol(const QrDesc* d, int nprob, int max_l, hipStream_t s)
 {
     if (nprob <= 0) return hipSuccess;
-    // panel (max_l x PSTR) and, afterwards, the diagonal blocks with their
-    // reciprocal diagonals (ceil(max_l/16) x (256 + 16))
-    const size_t lds = (size_t)std::max(max_l * PSTR, (max_l + 15) / 16 * 272) * sizeof(double);
+    const size_t lds = chol_lds_bytes(max_l);
     if (max_l <= 256)
-        hipLaunchKernelGGL(chol_kernel<256>, dim3(nprob), dim3(256), lds, s, d);
-    else if (max_l <= 512)
-        hipLaunchKernelGGL(chol_kernel<512>, dim3(nprob), dim3(512), lds, s, d);
+        hipLaunchKernelGGL(chol_rl_kernel<256>, dim3(nprob), dim3(256), lds, s, d);
     else
-        hipLaunchKernelGGL(chol_kernel<1024>, dim3(nprob), dim3(1024), lds, s, d);
+        hipLaunchKernelGGL(chol_rl_kernel<512>, dim3(nprob), dim3(512), lds, s, d);
     return hipGetLastError();
 }
 
@@ -533,16 +578,14 @@ hipError_t launch_trsm(const QrDesc* d, const int* row_begin, int nprob, int tot
 
 hipError_t init_qr_kernels()
 {
-    const int chol_lds = CHOL_MAX_L * PSTR * (int)sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void*)chol_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize, chol_lds);
+    hipError_t e = hipFuncSetAttribute((const void*)chol_rl_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)chol_lds_bytes(CHOL_MAX_L));
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)chol_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize, chol_lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)chol_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, chol_lds);
+        e = hipFuncSetAttribute((const void*)chol_rl_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)chol_lds_bytes(CHOL_MAX_L));
     if (e != hipSuccess) return e;
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)trsm_upper_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                16 * (CHOL_MAX_L + 1) * (int)sizeof(double));
+    e = hipFuncSetAttribute((const void*)trsm_upper_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       16 * (CHOL_MAX_L + 1) * (int)sizeof(double));
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void*)tri_prep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (CHOL_MAX_L / 16) * 272 * (int)sizeof(double));
