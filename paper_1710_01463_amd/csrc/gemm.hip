@@ -12,6 +12,8 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace rsvd {
 
 template <int GK> struct GemmCfg;
@@ -49,7 +51,7 @@ template <> struct OpConv<__bf16> {
 
 template <typename TC> __device__ __forceinline__ TC store_cvt(double x) { return from_f64<TC>(x); }
 
-template <int GK, typename TA, typename TX, typename TC>
+template <int GK, typename TA, typename TX, typename TC, int BM, int BN, bool GATHER>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs,
                                                     const int* __restrict__ tile_begin, int nprob)
 {
@@ -57,7 +59,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
     typedef typename GemmCfg<GK>::Acc4 Acc4;
     constexpr int BK = GemmCfg<GK>::BK;
     constexpr int LDK = BK + GemmCfg<GK>::PAD;
-    constexpr int BM = GEMM_BM, BN = GEMM_BN;
+    // 2 x 2 waves, each owning a WTM x WTN sub-tile of FM x FN MFMA 16 x 16 tiles
+    constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 16, FN = WTN / 16;
     __shared__ __attribute__((aligned(16))) OpT As[BM * LDK];
     __shared__ __attribute__((aligned(16))) OpT Xs[BN * LDK];
 
@@ -79,99 +82,124 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = (wave >> 1) * 32;
-    const int wn = (wave & 1) * 32;
+    const int wm = (wave >> 1) * WTM;
+    const int wn = (wave & 1) * WTN;
     const int l16 = lane & 15;
     const int lq = lane >> 4;
 
-    Acc4 acc[2][2];
+    Acc4 acc[FM][FN];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) acc[a][c] = Acc4{0, 0, 0, 0};
+        for (int c = 0; c < FN; ++c) acc[a][c] = Acc4{0, 0, 0, 0};
 
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        // ---- stage op(A) tile (BM x BK) as As[i][kk]
-        for (int e = tid; e < BM * BK; e += 256) {
-            int i, kk;
-            if (!transA) {
-                i = e / BK;
-                kk = e % BK;
-            } else {
-                kk = e / BM;
-                i = e % BM;
-            }
+    // Operand tiles are loaded into registers one K step ahead (the loads of
+    // step k + 1 are in flight while step k multiplies out of LDS).  Loads use
+    // a clamped in-bounds address and keep their raw element type; bounds and
+    // conversion are applied when the registers are written to LDS, so no
+    // instruction consumes a loaded value before the multiply is issued.
+    constexpr int NLA = BM * BK / 256, NLX = BK * BN / 256;
+    TA ra[NLA];
+    TX rx[NLX];
+    uint32_t oka = 0, okx = 0;
+    // Branch-free address arithmetic (transposition flags select, out-of-range
+    // elements read index 0 and are masked later): every load of a step is
+    // issued back to back.
+    auto load_tiles = [&](int k0) {
+        oka = 0;
+        okx = 0;
+#pragma unroll
+        for (int u = 0; u < NLA; ++u) {
+            const int e = tid + 256 * u;
+            const int i = transA ? e % BM : e / BK, kk = transA ? e / BM : e % BK;
             const int gi = m0 + i, gk = k0 + kk;
-            OpT v = OpConv<OpT>::cvt((TA)0);
-            if (gi < M && gk < K)
-                v = OpConv<OpT>::cvt(transA ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk]);
-            As[i * LDK + kk] = v;
+            const bool ok = gi < M && gk < K;
+            const int64_t off = transA ? (int64_t)gk * lda + gi : (int64_t)gi * lda + gk;
+            ra[u] = A[ok ? off : 0];
+            oka |= (uint32_t)ok << u;
         }
-        // ---- stage op(X) tile (BK x BN) as Xs[j][kk]
-        for (int e = tid; e < BK * BN; e += 256) {
-            int j, kk;
-            if (!transX) {
-                kk = e / BN;
-                j = e % BN;
-            } else {
-                j = e / BK;
-                kk = e % BK;
-            }
+        int rowv[NLX];
+#pragma unroll
+        for (int u = 0; u < NLX; ++u) {
+            const int e = tid + 256 * u;
+            const int j = transX ? e / BK : e % BN;
+            const int gj = n0 + j;
+            rowv[u] = gj;
+            if constexpr (GATHER) rowv[u] = gather[gj < N ? gj : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < NLX; ++u) {
+            const int e = tid + 256 * u;
+            const int j = transX ? e / BK : e % BN, kk = transX ? e % BK : e / BN;
             const int gj = n0 + j, gk = k0 + kk;
-            OpT v = OpConv<OpT>::cvt((TX)0);
-            if (gj < N && gk < K) {
-                if (!transX) {
-                    v = OpConv<OpT>::cvt(X[(int64_t)gk * ldx + gj]);
-                } else {
-                    const int row = gather ? gather[gj] : gj;
-                    v = OpConv<OpT>::cvt(X[(int64_t)row * ldx + gk]);
-                }
-            }
-            Xs[j * LDK + kk] = v;
+            const bool ok = gj < N && gk < K;
+            const int64_t off = transX ? (int64_t)rowv[u] * ldx + gk : (int64_t)gk * ldx + gj;
+            rx[u] = X[ok ? off : 0];
+            okx |= (uint32_t)ok << u;
+        }
+    };
+    load_tiles(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        // ---- registers -> LDS, k-contiguous: As[i][kk], Xs[j][kk]
+#pragma unroll
+        for (int u = 0; u < NLA; ++u) {
+            const int e = tid + 256 * u;
+            const int i = transA ? e % BM : e / BK, kk = transA ? e / BM : e % BK;
+            As[i * LDK + kk] = ((oka >> u) & 1u) ? OpConv<OpT>::cvt(ra[u]) : OpConv<OpT>::cvt((TA)0);
+        }
+#pragma unroll
+        for (int u = 0; u < NLX; ++u) {
+            const int e = tid + 256 * u;
+            const int j = transX ? e / BK : e % BN, kk = transX ? e % BK : e / BN;
+            Xs[j * LDK + kk] = ((okx >> u) & 1u) ? OpConv<OpT>::cvt(rx[u]) : OpConv<OpT>::cvt((TX)0);
         }
         __syncthreads();
+        if (k0 + BK < K) load_tiles(k0 + BK);
 
         if constexpr (GK == GK_F64) {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
-                double av[2], bv[2];
+                double av[FM], bv[FN];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) av[a] = As[(wm + a * 16 + l16) * LDK + kk + lq];
+                for (int a = 0; a < FM; ++a) av[a] = As[(wm + a * 16 + l16) * LDK + kk + lq];
 #pragma unroll
-                for (int c = 0; c < 2; ++c) bv[c] = Xs[(wn + c * 16 + l16) * LDK + kk + lq];
+                for (int c = 0; c < FN; ++c) bv[c] = Xs[(wn + c * 16 + l16) * LDK + kk + lq];
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
+                for (int a = 0; a < FM; ++a)
 #pragma unroll
-                    for (int c = 0; c < 2; ++c)
+                    for (int c = 0; c < FN; ++c)
                         acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[c], acc[a][c], 0, 0, 0);
             }
         } else if constexpr (GK == GK_F32) {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
-                float av[2], bv[2];
+                float av[FM], bv[FN];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) av[a] = As[(wm + a * 16 + l16) * LDK + kk + lq];
+                for (int a = 0; a < FM; ++a) av[a] = As[(wm + a * 16 + l16) * LDK + kk + lq];
 #pragma unroll
-                for (int c = 0; c < 2; ++c) bv[c] = Xs[(wn + c * 16 + l16) * LDK + kk + lq];
+                for (int c = 0; c < FN; ++c) bv[c] = Xs[(wn + c * 16 + l16) * LDK + kk + lq];
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
+                for (int a = 0; a < FM; ++a)
 #pragma unroll
-                    for (int c = 0; c < 2; ++c)
+                    for (int c = 0; c < FN; ++c)
                         acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[c], acc[a][c], 0, 0, 0);
             }
         } else {
-            bf16x8 av[2], bv[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-                av[a] = *reinterpret_cast<const bf16x8*>(&As[(wm + a * 16 + l16) * LDK + 8 * lq]);
+            for (int kk = 0; kk < BK; kk += 32) {
+                bf16x8 av[FM], bv[FN];
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
-                bv[c] = *reinterpret_cast<const bf16x8*>(&Xs[(wn + c * 16 + l16) * LDK + 8 * lq]);
+                for (int a = 0; a < FM; ++a)
+                    av[a] = *reinterpret_cast<const bf16x8*>(&As[(wm + a * 16 + l16) * LDK + kk + 8 * lq]);
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+                for (int c = 0; c < FN; ++c)
+                    bv[c] = *reinterpret_cast<const bf16x8*>(&Xs[(wn + c * 16 + l16) * LDK + kk + 8 * lq]);
 #pragma unroll
-                for (int c = 0; c < 2; ++c)
-                    acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[c], acc[a][c], 0, 0, 0);
+                for (int a = 0; a < FM; ++a)
+#pragma unroll
+                    for (int c = 0; c < FN; ++c)
+                        acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[c], acc[a][c], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
@@ -181,9 +209,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
     const int64_t ldc = d.ldc;
     const int transC = d.transC, accumulate = d.accumulate;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < FN; ++c)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int i, j;
@@ -204,56 +232,81 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
 }
 
 template <int GK, typename TA, typename TX, typename TC>
-static hipError_t launch_t(const GemmDesc* descs, const int* tile_begin, int nprob, int total,
-                           hipStream_t s)
+static hipError_t launch_t(GemmTile tile, bool gather, const GemmDesc* descs, const int* tile_begin, int nprob,
+                           int total, hipStream_t s)
 {
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL((gemm_kernel<GK, TA, TX, TC>), dim3(total), dim3(256), 0, s, descs, tile_begin,
-                       nprob);
+    if (gather) {
+        // the gathered product (U = Q Utilde[:, perm]) is small and FP64: one tile shape
+        if constexpr (GK == GK_F64 && std::is_same<TA, double>::value && std::is_same<TX, double>::value) {
+            hipLaunchKernelGGL((gemm_kernel<GK, TA, TX, TC, 64, 64, true>), dim3(total), dim3(256), 0, s, descs,
+                               tile_begin, nprob);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
+    switch (tile) {
+    case GT_64x64:
+        hipLaunchKernelGGL((gemm_kernel<GK, TA, TX, TC, 64, 64, false>), dim3(total), dim3(256), 0, s, descs, tile_begin, nprob);
+        break;
+    case GT_128x64:
+        hipLaunchKernelGGL((gemm_kernel<GK, TA, TX, TC, 128, 64, false>), dim3(total), dim3(256), 0, s, descs, tile_begin, nprob);
+        break;
+    case GT_64x128:
+        hipLaunchKernelGGL((gemm_kernel<GK, TA, TX, TC, 64, 128, false>), dim3(total), dim3(256), 0, s, descs, tile_begin, nprob);
+        break;
+    case GT_128x128:
+        hipLaunchKernelGGL((gemm_kernel<GK, TA, TX, TC, 128, 128, false>), dim3(total), dim3(256), 0, s, descs, tile_begin, nprob);
+        break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 template <int GK, typename TA, typename TX>
-static hipError_t launch_c(Elem ec, const GemmDesc* d, const int* tb, int np, int tot, hipStream_t s)
+static hipError_t launch_c(Elem ec, GemmTile tl, bool g, const GemmDesc* d, const int* tb, int np, int tot, hipStream_t s)
 {
     switch (ec) {
-    case E_F64: return launch_t<GK, TA, TX, double>(d, tb, np, tot, s);
-    case E_F32: return launch_t<GK, TA, TX, float>(d, tb, np, tot, s);
+    case E_F64: return launch_t<GK, TA, TX, double>(tl, g, d, tb, np, tot, s);
+    case E_F32: return launch_t<GK, TA, TX, float>(tl, g, d, tb, np, tot, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <int GK, typename TA>
-static hipError_t launch_x(Elem ex, Elem ec, const GemmDesc* d, const int* tb, int np, int tot,
+static hipError_t launch_x(Elem ex, Elem ec, GemmTile tl, bool g, const GemmDesc* d, const int* tb, int np, int tot,
                            hipStream_t s)
 {
     switch (ex) {
-    case E_F64: return launch_c<GK, TA, double>(ec, d, tb, np, tot, s);
-    case E_F32: return launch_c<GK, TA, float>(ec, d, tb, np, tot, s);
-    case E_BF16: return launch_c<GK, TA, __bf16>(ec, d, tb, np, tot, s);
+    case E_F64: return launch_c<GK, TA, double>(ec, tl, g, d, tb, np, tot, s);
+    case E_F32: return launch_c<GK, TA, float>(ec, tl, g, d, tb, np, tot, s);
+    case E_BF16: return launch_c<GK, TA, __bf16>(ec, tl, g, d, tb, np, tot, s);
     }
     return hipErrorInvalidValue;
 }
 
 template <int GK>
-static hipError_t launch_a(Elem ea, Elem ex, Elem ec, const GemmDesc* d, const int* tb, int np, int tot,
-                           hipStream_t s)
+static hipError_t launch_a(Elem ea, Elem ex, Elem ec, GemmTile tl, bool g, const GemmDesc* d, const int* tb, int np,
+                           int tot, hipStream_t s)
 {
     switch (ea) {
-    case E_F64: return launch_x<GK, double>(ex, ec, d, tb, np, tot, s);
-    case E_F32: return launch_x<GK, float>(ex, ec, d, tb, np, tot, s);
-    case E_BF16: return launch_x<GK, __bf16>(ex, ec, d, tb, np, tot, s);
+    case E_F64: return launch_x<GK, double>(ex, ec, tl, g, d, tb, np, tot, s);
+    case E_F32: return launch_x<GK, float>(ex, ec, tl, g, d, tb, np, tot, s);
+    case E_BF16: return launch_x<GK, __bf16>(ex, ec, tl, g, d, tb, np, tot, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_gemm(GemmKind kind, Elem ea, Elem ex, Elem ec, const GemmDesc* descs,
+hipError_t launch_gemm(GemmKind kind, Elem ea, Elem ex, Elem ec, GemmTile tile, bool gather, const GemmDesc* descs,
                        const int* tile_begin, int nprob, int total_tiles, hipStream_t stream)
 {
+    if (gather && !(kind == GK_F64 && ea == E_F64 && ex == E_F64)) return hipErrorInvalidValue;
+    if (gather) tile = GT_64x64;
     switch (kind) {
-    case GK_F64: return launch_a<GK_F64>(ea, ex, ec, descs, tile_begin, nprob, total_tiles, stream);
-    case GK_F32: return launch_a<GK_F32>(ea, ex, ec, descs, tile_begin, nprob, total_tiles, stream);
-    case GK_BF16: return launch_a<GK_BF16>(ea, ex, ec, descs, tile_begin, nprob, total_tiles, stream);
+    case GK_F64: return launch_a<GK_F64>(ea, ex, ec, tile, gather, descs, tile_begin, nprob, total_tiles, stream);
+    case GK_F32: return launch_a<GK_F32>(ea, ex, ec, tile, false, descs, tile_begin, nprob, total_tiles, stream);
+    case GK_BF16: return launch_a<GK_BF16>(ea, ex, ec, tile, false, descs, tile_begin, nprob, total_tiles, stream);
     }
     return hipErrorInvalidValue;
 }

@@ -33,14 +33,18 @@ enum GemmKind : int {
 
 enum Elem : int { E_F64 = 0, E_F32 = 1, E_BF16 = 2 };
 
-constexpr int GEMM_BM = 64;
-constexpr int GEMM_BN = 64;
+// Workgroup output tile of a GEMM launch (256 threads, 2 x 2 waves).
+enum GemmTile : int { GT_64x64 = 0, GT_128x64 = 1, GT_64x128 = 2, GT_128x128 = 3 };
+constexpr int gemm_tile_m(GemmTile t) { return (t == GT_128x64 || t == GT_128x128) ? 128 : 64; }
+constexpr int gemm_tile_n(GemmTile t) { return (t == GT_64x128 || t == GT_128x128) ? 128 : 64; }
 
 // descs: device array of nprob descriptors; tile_begin: the launch's work-item map,
-// total_tiles int pairs (problem, tile index), a problem with ceil(M/64) * ceil(N/64)
-// tiles contributing that many consecutive entries.  Every "*_begin" argument of
+// total_tiles int pairs (problem, tile index), a problem with ceil(M/BM) * ceil(N/BN)
+// tiles contributing that many consecutive entries (BM x BN = the launch's GemmTile;
+// tiles_n of every descriptor must be ceil(N/BN)).  Every "*_begin" argument of
 // the launchers below is such a map over that launch's items.
-hipError_t launch_gemm(GemmKind kind, Elem ea, Elem ex, Elem ec, const GemmDesc* descs,
+// gather: the descriptors carry gather arrays (FP64 operands only; tile forced to 64 x 64).
+hipError_t launch_gemm(GemmKind kind, Elem ea, Elem ex, Elem ec, GemmTile tile, bool gather, const GemmDesc* descs,
                        const int* tile_begin, int nprob, int total_tiles, hipStream_t stream);
 
 // ---------------------------------------------------------------- QR (orthonormalisation)

@@ -78,6 +78,8 @@ struct ProbHost {
 
 struct GemmLaunch {
     GemmKind kind;
+    GemmTile tile;
+    bool gather;
     Elem ea, ex, ec;
     size_t off_desc, off_begin;
     int total;
@@ -305,7 +307,25 @@ void layout(rsvd_plan& P)
 
 template <typename T> T* wsp(const rsvd_plan& P, size_t off) { return (T*)(P.ws + off); }
 
-int tiles_of(int M, int N) { return ((M + GEMM_BM - 1) / GEMM_BM) * ((N + GEMM_BN - 1) / GEMM_BN); }
+int tiles_of(int M, int N, GemmTile t)
+{
+    const int bm = gemm_tile_m(t), bn = gemm_tile_n(t);
+    return ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+}
+
+// Workgroup tile of a GEMM launch: 128 x 64 for tall, narrow products with
+// enough tiles to fill the GPU twice over, else 64 x 64.
+GemmTile choose_tile(const std::vector<GemmDesc>& descs)
+{
+    int64_t tiles128 = 0;
+    bool tall = true;
+    for (const GemmDesc& d : descs) {
+        if (d.A == nullptr || d.M <= 0 || d.N <= 0) continue;
+        tiles128 += tiles_of(d.M, d.N, GT_128x64);
+        if (!(d.M >= 512 && d.N <= 160)) tall = false;
+    }
+    return (tall && tiles128 >= 512) ? GT_128x64 : GT_64x64;
+}
 
 // Work-item map of a batched launch: entry t = (problem, local item) for
 // workgroup t, problems in order, count[b] items each.
@@ -323,18 +343,23 @@ std::vector<int> item_map(const std::vector<int>& counts)
 
 GemmLaunch add_gemm(Blob& B, GemmKind kind, Elem ea, Elem ex, Elem ec, std::vector<GemmDesc>& descs)
 {
+    bool gather = false;
+    for (const GemmDesc& d : descs) gather = gather || (d.A != nullptr && d.gather != nullptr);
+    const GemmTile tile = gather ? GT_64x64 : choose_tile(descs);
     std::vector<int> counts(descs.size(), 0);
     int total = 0;
     for (size_t b = 0; b < descs.size(); ++b) {
         GemmDesc& d = descs[b];
         int t = 0;
-        if (d.M > 0 && d.N > 0 && d.K >= 0 && d.A != nullptr) t = tiles_of(d.M, d.N);
-        d.tiles_n = (d.N + GEMM_BN - 1) / GEMM_BN;
+        if (d.M > 0 && d.N > 0 && d.K >= 0 && d.A != nullptr) t = tiles_of(d.M, d.N, tile);
+        d.tiles_n = (d.N + gemm_tile_n(tile) - 1) / gemm_tile_n(tile);
         counts[b] = t;
         total += t;
     }
     GemmLaunch g;
     g.kind = kind;
+    g.tile = tile;
+    g.gather = gather;
     g.ea = ea;
     g.ex = ex;
     g.ec = ec;
@@ -644,7 +669,7 @@ int gemm(const rsvd_plan& P, const GemmLaunch& g, hipStream_t s, int cat)
 {
     if (g.total <= 0) return RSVD_OK;
     PLAUNCH(cat, g.flops,
-            launch_gemm(g.kind, g.ea, g.ex, g.ec, dp<GemmDesc>(P, g.off_desc), dp<int>(P, g.off_begin), P.nprob,
+            launch_gemm(g.kind, g.ea, g.ex, g.ec, g.tile, g.gather, dp<GemmDesc>(P, g.off_desc), dp<int>(P, g.off_begin), P.nprob,
                         g.total, s));
     return RSVD_OK;
 }
@@ -868,7 +893,7 @@ int enqueue_backward(rsvd_plan& P, hipStream_t s)
     auto bgemm = [&](const GemmLaunch& g) -> int {
         if (g.total <= 0) return RSVD_OK;
         PLAUNCH(RSVD_PHASE_BW_GEMM, g.flops,
-                launch_gemm(g.kind, g.ea, g.ex, g.ec, (const GemmDesc*)dd(g.off_desc), (const int*)dd(g.off_begin),
+                launch_gemm(g.kind, g.ea, g.ex, g.ec, g.tile, g.gather, (const GemmDesc*)dd(g.off_desc), (const int*)dd(g.off_begin),
                             np, g.total, s));
         return RSVD_OK;
     };
