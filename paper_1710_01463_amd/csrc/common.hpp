@@ -62,6 +62,15 @@ template <> __device__ __forceinline__ __bf16 from_f32<__bf16>(float x)
     return __builtin_bit_cast(__bf16, hi);
 }
 
+// p[idx] if ok, else 0, as an unconditional load from a clamped address: no
+// branch around the load, so that a group of such loads is issued back to
+// back and waited for once (a load under a branch ends the branch with a wait).
+template <typename T> __device__ __forceinline__ T ld_or0(const GLB T* p, int64_t idx, bool ok)
+{
+    const T v = p[ok ? idx : 0];
+    return ok ? v : (T)0;
+}
+
 // Wave-level reductions (64 lanes) with shuffles.
 __device__ __forceinline__ double wave_sum(double v)
 {

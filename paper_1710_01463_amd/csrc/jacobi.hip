@@ -74,7 +74,7 @@ __device__ __forceinline__ void load_chunk(double (&pre)[JPF], const GLB double*
         const int e = tid + JT * i;
         const int a = e / JCH, cc = e % JCH;
         const int gr = rowmap[a], gc = c0 + cc;
-        pre[i] = (gr >= 0 && gc < ncols) ? M[(int64_t)gr * ldm + gc] : 0.0;
+        pre[i] = ld_or0(M, (int64_t)gr * ldm + gc, gr >= 0 && gc < ncols);
     }
 }
 __device__ __forceinline__ void store_chunk(const double (&pre)[JPF], double (*Xs)[JCH + 1])
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinDesc* __restrict__
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int t = t0 + 64 * u;
-                v[u] = (t < C) ? X[(int64_t)i * d.ldx + t] : 0.0;
+                v[u] = ld_or0(X, (int64_t)i * d.ldx + t, t < C);
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) s = fma(v[u], v[u], s);

@@ -70,8 +70,9 @@ constexpr int CHOL_MAX_L = 1024;
 hipError_t launch_chol(const QrDesc* d, int nprob, int max_l, hipStream_t s);
 // Qout = src L^-T, src = Min (from_min = 1) or Qout (from_min = 0, in place);
 // row_begin: item map over the ceil(rows / 16) row blocks of every problem.
+// src_elem: element type of Min when from_min (E_F64 or E_F32).
 hipError_t launch_trsm(const QrDesc* d, const int* row_begin, int nprob, int total_blocks, int from_min,
-                       int max_l, hipStream_t s);
+                       int src_elem, int max_l, hipStream_t s);
 // Raises the dynamic-LDS limit of the Cholesky kernel.
 hipError_t init_qr_kernels();
 // Householder QR of Min into Qout for the problems whose flag is set.

@@ -699,13 +699,13 @@ int enqueue(rsvd_plan& P, hipStream_t s)
             if ((rc = gemm(P, P.g_gram1[st], s, RSVD_PHASE_GRAM)) != RSVD_OK) return rc;
             PLAUNCH(RSVD_PHASE_CHOL, 0.0, launch_chol(dp<QrDesc>(P, q1.off_desc), np, P.max_l, s));
             PLAUNCH(RSVD_PHASE_TRSM, 0.0,
-                    launch_trsm(dp<QrDesc>(P, t1.off_desc), dp<int>(P, t1.off_begin), np, t1.total, 1, P.max_l, s));
+                    launch_trsm(dp<QrDesc>(P, t1.off_desc), dp<int>(P, t1.off_begin), np, t1.total, 1, P.e_y, P.max_l, s));
             // pass 2 for the problems whose final basis this is
             if (t2.total > 0) {
                 if ((rc = gemm(P, P.g_gram2[st], s, RSVD_PHASE_GRAM)) != RSVD_OK) return rc;
                 PLAUNCH(RSVD_PHASE_CHOL, 0.0, launch_chol(dp<QrDesc>(P, q2.off_desc), np, P.max_l, s));
                 PLAUNCH(RSVD_PHASE_TRSM, 0.0,
-                        launch_trsm(dp<QrDesc>(P, t2.off_desc), dp<int>(P, t2.off_begin), np, t2.total, 0, P.max_l, s));
+                        launch_trsm(dp<QrDesc>(P, t2.off_desc), dp<int>(P, t2.off_begin), np, t2.total, 0, E_F64, P.max_l, s));
             }
             // Householder for the problems whose Cholesky QR broke down
             PLAUNCH(RSVD_PHASE_HOUSEHOLDER, 0.0, launch_householder(dp<QrDesc>(P, q1.off_desc), np, s));

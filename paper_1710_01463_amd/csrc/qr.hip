@@ -139,7 +139,8 @@ __global__ __launch_bounds__(NT) void chol_rl_kernel(const QrDesc* __restrict__ 
             double a[16];
 #pragma unroll
             for (int c = 0; c < 16; ++c)
-                a[c] = (r < w && c < w && c <= r) ? G[(int64_t)(J + r) * l + J + c] : (r == c ? 1.0 : 0.0);
+                a[c] = (r < w && c < w && c <= r) ? ld_or0(G, (int64_t)(J + r) * l + J + c, r < w && c < w)
+                                                  : (r == c ? 1.0 : 0.0);
             bool bad = false;
             double dinv = 1.0;
 #pragma unroll
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(NT) void chol_rl_kernel(const QrDesc* __restrict__ 
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) {
                 const int k = 4 * s4 + lq;
-                av[s4] = (I0 + l16 < l && k < w) ? G[(int64_t)(I0 + l16) * l + J + k] : 0.0;
+                av[s4] = ld_or0(G, (int64_t)(I0 + l16) * l + J + k, I0 + l16 < l && k < w);
             }
             dbl4 acc = {0, 0, 0, 0};
 #pragma unroll
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(NT) void chol_rl_kernel(const QrDesc* __restrict__ 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = J + 16 + 16 * a + lq + 4 * r, j = J + 16 + 16 * rem + l16;
-                    acc[g][r] = (t < ntile && i < l && j < l) ? G[(int64_t)i * l + j] : 0.0;
+                    acc[g][r] = ld_or0(G, (int64_t)i * l + j, t < ntile && i < l && j < l);
                 }
             }
 #pragma unroll
@@ -264,6 +265,7 @@ __global__ __launch_bounds__(NT) void chol_rl_kernel(const QrDesc* __restrict__ 
 // D_C (M^T[C] - L[C, :C] Q^T[:C]); both products are FP64 MFMA chains, the
 // accumulator of the first feeding the second directly as its B operand.  The
 // wave's 16 rows of Q stay in LDS; no other wave reads them.
+template <typename TS>
 __global__ __launch_bounds__(64) void trsm_kernel(const QrDesc* __restrict__ descs,
                                                   const int* __restrict__ row_begin, int nprob, int from_min)
 {
@@ -290,11 +292,8 @@ __global__ __launch_bounds__(64) void trsm_kernel(const QrDesc* __restrict__ des
         for (int u = 0; u < 8; ++u) {
             const int e = base + 64 * u;
             const int r = e / l, c = e % l;
-            v[u] = 0.0;
-            if (e < 16 * l && r < nr) {
-                const int64_t gi = (int64_t)(r0 + r) * l + c;
-                v[u] = from_min ? ld_elem(d.Min, d.min_elem, gi) : Qout[gi];
-            }
+            const GLB TS* src = from_min ? (const GLB TS*)d.Min : (const GLB TS*)Qout;
+            v[u] = to_f64(ld_or0(src, (int64_t)(r0 + r) * l + c, e < 16 * l && r < nr));
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -318,7 +317,7 @@ __global__ __launch_bounds__(64) void trsm_kernel(const QrDesc* __restrict__ des
             for (int u = 0; u < 8; ++u) {
                 const int kc = k0 + 4 * u + lq;
                 const bool ok = kc < C0;
-                av[u] = (ok && ra < l) ? -Rt[(int64_t)kc * l + ra] : 0.0;
+                av[u] = -ld_or0(Rt, (int64_t)kc * l + ra, ok && ra < l);
                 bv[u] = ok ? Qs[l16 * ldq + kc] : 0.0;
             }
 #pragma unroll
@@ -393,7 +392,7 @@ __global__ __launch_bounds__(64) void trsm_upper_kernel(const QrDesc* __restrict
         for (int u = 0; u < 8; ++u) {
             const int e = base + 64 * u;
             const int r = e / l, c = e % l;
-            v[u] = (e < 16 * l && r < nr) ? Qout[(int64_t)(r0 + r) * l + c] : 0.0;
+            v[u] = ld_or0((const GLB double*)Qout, (int64_t)(r0 + r) * l + c, e < 16 * l && r < nr);
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -418,7 +417,7 @@ __global__ __launch_bounds__(64) void trsm_upper_kernel(const QrDesc* __restrict
             for (int u = 0; u < 8; ++u) {
                 const int kc = k0 + 4 * u + lq;
                 const bool ok = kc < l;
-                av[u] = (ok && ci < l) ? -Rt[(int64_t)ci * l + kc] : 0.0;
+                av[u] = -ld_or0(Rt, (int64_t)ci * l + kc, ok && ci < l);
                 bv[u] = ok ? Qs[l16 * ldq + kc] : 0.0;
             }
 #pragma unroll
@@ -568,11 +567,16 @@ hipError_t launch_chol(const QrDesc* d, int nprob, int max_l, hipStream_t s)
 }
 
 hipError_t launch_trsm(const QrDesc* d, const int* row_begin, int nprob, int total_blocks, int from_min,
-                       int max_l, hipStream_t s)
+                       int src_elem, int max_l, hipStream_t s)
 {
     if (total_blocks <= 0) return hipSuccess;
     const size_t lds = (size_t)16 * (max_l + 1) * sizeof(double);
-    hipLaunchKernelGGL(trsm_kernel, dim3(total_blocks), dim3(64), lds, s, d, row_begin, nprob, from_min);
+    if (from_min && src_elem == E_F32)
+        hipLaunchKernelGGL(trsm_kernel<float>, dim3(total_blocks), dim3(64), lds, s, d, row_begin, nprob, from_min);
+    else if (!from_min || src_elem == E_F64)
+        hipLaunchKernelGGL(trsm_kernel<double>, dim3(total_blocks), dim3(64), lds, s, d, row_begin, nprob, from_min);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -590,7 +594,10 @@ hipError_t init_qr_kernels()
         e = hipFuncSetAttribute((const void*)tri_prep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (CHOL_MAX_L / 16) * 272 * (int)sizeof(double));
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)trsm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+    e = hipFuncSetAttribute((const void*)trsm_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            16 * (CHOL_MAX_L + 1) * (int)sizeof(double));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)trsm_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                16 * (CHOL_MAX_L + 1) * (int)sizeof(double));
 }
 
