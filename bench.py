@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--no-diff", action="store_true", help="skip the forward + adjoint leg")
     ap.add_argument("--diff-batch", type=int, default=64)
     ap.add_argument("--diff-steps", type=int, default=5)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -67,6 +69,25 @@ def cpu_baseline(mats, probs, sample):
     return {"value": len(idx) / dt, "unit": "RSVDs/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(idx)} of the {len(mats)} matrices (512x512, k=256 p=16 q=2), "
                       f"FP64 C oracle, one matrix per thread, {dt:.1f} s wall"}
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the FETCH_SIZE/WRITE_SIZE passes
+    summarised under profiles/, or None when no pass was taken or the kernel's
+    source changed since (the summary records the source's SHA-1)."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic_bytes_per_launch "):
+                continue
+            f = dict(kv.split("=", 1) for kv in line.split()[1:])
+            if f.get("kernel") != kernel or f.get("workload") != workload:
+                continue
+            src = os.path.join(ROOT, f["source"])
+            if os.path.exists(src) and hashlib.sha1(open(src, "rb").read()).hexdigest() == f["sha1"]:
+                return float(f["bytes"])
+    return None
 
 
 def gen_matrices(probs, dtype):
@@ -148,6 +169,16 @@ def main():
     import workloads as wl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_mib:
+        # a plain copy kernel of known size, for scaling FETCH_SIZE / WRITE_SIZE counters
+        n = args.copy_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "copies": 3}))
+        return
     W = wl.c2(args.batch)
     probs = W.problems
     log(f"[bench] generating {len(probs)} matrices {probs[0].m}x{probs[0].n}")
@@ -208,7 +239,7 @@ def main():
     peak = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}["f64" if dom != "sketch" else args.prec]
     achieved = (fl_dom / n_dom) / (ms_dom / n_dom * 1e-3) / 1e12 if n_dom and ms_dom else 0.0
     result["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                          "frac": achieved / peak, "traffic": None,
+                          "frac": achieved / peak, "traffic": measured_traffic(kernel_of.get(dom, dom), "C2") if args.prec == "f64" else None,
                           "kernel": kernel_of.get(dom, dom), "phase": dom,
                           "avg_launch_us": ms_dom / n_dom * 1e3 if n_dom else None,
                           "launches_per_step": n_dom,
