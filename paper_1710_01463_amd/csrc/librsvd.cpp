@@ -34,12 +34,16 @@ int fail(int code, const std::string& msg)
         if (e_ != hipSuccess) return fail(RSVD_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// Sweep caps of the block Jacobi: the small SVD of B converges in 6-9 sweeps on
-// every workload measured (the last one only confirms convergence), the full
-// SVD in more.  Every sweep past convergence still costs one graph node per
-// round (a few microseconds each), so the cap is kept near the need; a problem
-// that reaches it reports RSVD_ERR_NOCONV with its results filled in.
+// Sweep caps of the block Jacobi.  The small SVD of B converges in 6-9 sweeps
+// for l <= 272 on every workload measured (the last sweep only confirms
+// convergence); wider sketches of steep spectra (l >= 288 with tails far below
+// the working precision) need more.  Every sweep past convergence still costs
+// one graph node per round (a few microseconds each), so the cap follows the
+// widest sketch of the plan; a problem that reaches it reports
+// RSVD_ERR_NOCONV with its results filled in.
 constexpr int JAC_MAX_SWEEPS_RSVD = 14;
+constexpr int JAC_MAX_SWEEPS_RSVD_WIDE = 30;
+constexpr int JAC_WIDE_L = 272;
 constexpr int JAC_MAX_SWEEPS_FULL = 30;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -1026,7 +1030,7 @@ int plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsv
     P->prec = fullsvd ? RSVD_PREC_F64 : prec;
     P->flags = flags;
     P->fullsvd = fullsvd;
-    P->max_sweeps = fullsvd ? JAC_MAX_SWEEPS_FULL : JAC_MAX_SWEEPS_RSVD;
+    P->max_sweeps = JAC_MAX_SWEEPS_FULL;
     P->e_store = store_elem(dt);
     P->e_sketch = P->prec == RSVD_PREC_F64 ? E_F64 : (P->prec == RSVD_PREC_F32 ? E_F32 : E_BF16);
     P->e_y = P->prec == RSVD_PREC_F64 ? E_F64 : E_F32;
@@ -1065,6 +1069,7 @@ int plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsv
         P->max_nb = std::max(P->max_nb, h.nb);
         P->max_q = std::max<int>(P->max_q, (int)h.q);
     }
+    if (!fullsvd) P->max_sweeps = P->max_l > JAC_WIDE_L ? JAC_MAX_SWEEPS_RSVD_WIDE : JAC_MAX_SWEEPS_RSVD;
     layout(*P);
     {
         static std::once_flag once;
