@@ -174,9 +174,9 @@ enum {
 /* rsvd_plan_profile -- one execute run without the graph, with HIP events
  * around every launch on stream.  For each phase c < ncat: ms[c] = summed
  * kernel time, launches[c] = number of launches, flops[c] = algorithmic FLOPs
- * (GEMMs: 2 M N K per problem; Jacobi: 2 * 32 * 32 * C for every block-pair
- * Gram formed plus 2 * 32 * 32 * (C + R) for every rotation applied; other
- * phases 0).  Arguments otherwise as rsvd_plan_execute.  Blocking. */
+ * (GEMMs: 2 M N K per problem; Jacobi: 2 b^2 C for every block-pair Gram
+ * formed plus 2 b^2 (C + R) for every rotation applied, b = rows per block
+ * pair (32); other phases 0).  Arguments otherwise as rsvd_plan_execute.  Blocking. */
 int rsvd_plan_profile(rsvd_plan_t* plan, const void* const* A, void* const* U, void* const* S,
                       void* const* VT, double* discarded_weight, int64_t* k_kept, int* info,
                       double* ms, int64_t* launches, double* flops, int ncat, void* stream);

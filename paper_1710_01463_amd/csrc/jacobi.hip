@@ -5,23 +5,29 @@
 //
 // The vectors being orthogonalised are the R rows of X (R x C, R <= C); the
 // left rotations are accumulated in P (R x R), so that P X_in = X_out with
-// mutually orthogonal rows.  Rows are grouped in blocks of 16.  One launch is
-// one round of the round-robin schedule over the nb blocks: each workgroup
-// takes one block pair (32 rows), forms their 32 x 32 Gram matrix with FP64
-// MFMA, checks the relative off-diagonal |h_ij| <= tol sqrt(h_ii h_jj), and
-// if needed diagonalises it by cyclic two-sided Jacobi in LDS, then applies
-// the accumulated 32 x 32 rotation to the 32 rows of X and of P with FP64
-// MFMA.  A sweep is nb - 1 rounds; a problem is converged after a sweep in
+// mutually orthogonal rows.  Rows are grouped in blocks of JAC_B.  One launch
+// is one round of the round-robin schedule over the nb blocks: each workgroup
+// takes one block pair (JR = 2 JAC_B rows), forms their JR x JR Gram matrix
+// with FP64 MFMA, checks the relative off-diagonal |h_ij| <= tol
+// sqrt(h_ii h_jj), and if needed diagonalises it by one sweep of cyclic
+// two-sided Jacobi in LDS, then applies the accumulated JR x JR rotation to
+// the JR rows of X and of P with FP64 MFMA.  A sweep is nb - 1 rounds; a problem is converged after a sweep in
 // which no block pair needed a rotation.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace rsvd {
 
-constexpr int JR = 2 * JAC_B;  // rows per block pair
-constexpr int JCH = 128;       // column chunk staged through LDS
-constexpr int JT = 512;              // threads per workgroup
-constexpr int JPF = JR * JCH / JT;   // prefetched doubles per thread
+constexpr int JR = 2 * JAC_B;                    // rows per block pair
+constexpr int JNP = JR / 2;                      // plane pairs per inner step
+constexpr int JHB = JNP * JNP;                   // 2 x 2 blocks of the pair's Gram
+constexpr int JT = (2 * JHB <= 1024) ? 2 * JHB : JHB;  // threads per workgroup
+constexpr bool JSPLIT = JT == 2 * JHB;           // separate threads update P
+constexpr int JCH = JR >= 64 ? 64 : 128;         // column chunk staged through LDS
+constexpr int JPF = JR * JCH / JT;               // prefetched doubles per thread
+constexpr int JTILES = (JR / 16) * (JR / 16);    // 16 x 16 Gram tiles
+constexpr int JKS = (JT / 64) / JTILES;          // waves sharing one Gram tile (k split)
+static_assert(JKS >= 1 && (JT / 64) % JTILES == 0, "Gram tiling");
 
 __device__ __forceinline__ int rr_block(int pos, int round, int nb)
 {
@@ -128,23 +134,19 @@ __device__ void apply_rotation(const ChunkSeq& cs, double (&pre)[JPF], const int
         int64_t ldm;
         int ncols, c0;
         cs.select(ci, M, ldm, ncols, c0);
+        // (JR / 16) x (JCH / 16) output tiles of 16 x 16, spread over the waves
+        for (int tl = wave; tl < (JR / 16) * (JCH / 16); tl += JT / 64) {
+            const int rt = tl / (JCH / 16), tj = tl % (JCH / 16);
+            dbl4 acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int tj = wave; tj < JCH / 16; tj += JT / 64) {
-            dbl4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-#pragma unroll
-            for (int kk = 0; kk < JR; kk += 4) {
-                const double bv = Xs[kk + lq][tj * 16 + l16];
-                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ps[l16][kk + lq], bv, acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ps[16 + l16][kk + lq], bv, acc1, 0, 0, 0);
-            }
+            for (int kk = 0; kk < JR; kk += 4)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ps[rt * 16 + l16][kk + lq], Xs[kk + lq][tj * 16 + l16], acc,
+                                                           0, 0, 0);
             const int gc = c0 + tj * 16 + l16;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int g0 = rowmap[lq + 4 * r], g1 = rowmap[16 + lq + 4 * r];
-                if (gc < ncols) {
-                    if (g0 >= 0) M[(int64_t)g0 * ldm + gc] = acc0[r];
-                    if (g1 >= 0) M[(int64_t)g1 * ldm + gc] = acc1[r];
-                }
+                const int g = rowmap[rt * 16 + lq + 4 * r];
+                if (gc < ncols && g >= 0) M[(int64_t)g * ldm + gc] = acc[r];
             }
         }
         __syncthreads();
@@ -188,11 +190,12 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
     if (tid == 0) any_rot = 0;
     __syncthreads();
 
-    // ---- Gram matrix of the 32 rows (FP64 MFMA): wave w forms the 16 x 16
-    // tile (w / 2 % 2, w % 2) over one half of every column chunk; the two
-    // halves are added through LDS
+    // ---- Gram matrix of the JR rows (FP64 MFMA): wave w forms the 16 x 16
+    // tile (w % JTILES) over its share (w / JTILES of JKS) of every column
+    // chunk; with JKS = 2 the two halves are added through LDS
     {
-        const int wi = (wave >> 1) & 1, wj = wave & 1, half = wave >> 2;
+        const int tile = wave % JTILES;
+        const int wi = tile / (JR / 16), wj = tile % (JR / 16), half = wave / JTILES;
         dbl4 acc = {0, 0, 0, 0};
         double pre[JPF];
         load_chunk(pre, X, ldx, C, 0, rowmap);
@@ -201,14 +204,15 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
             __syncthreads();
             if (c0 + JCH < C) load_chunk(pre, X, ldx, C, c0 + JCH, rowmap);
 #pragma unroll 8
-            for (int kk = half * (JCH / 2); kk < (half + 1) * (JCH / 2); kk += 4) {
+            for (int kk = half * (JCH / JKS); kk < (half + 1) * (JCH / JKS); kk += 4) {
                 const double av = Xs[wi * 16 + l16][kk + lq];
                 const double bv = Xs[wj * 16 + l16][kk + lq];
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
             }
             __syncthreads();
         }
-        if (half == 1) {
+        static_assert(JKS <= 2, "Gram halves");
+        if (JKS == 2 && half == 1) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) Hbuf[1][wi * 16 + lq + 4 * r][wj * 16 + l16] = acc[r];
         }
@@ -216,7 +220,8 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
         if (half == 0) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                Hbuf[0][wi * 16 + lq + 4 * r][wj * 16 + l16] = acc[r] + Hbuf[1][wi * 16 + lq + 4 * r][wj * 16 + l16];
+                Hbuf[0][wi * 16 + lq + 4 * r][wj * 16 + l16] =
+                    acc[r] + (JKS == 2 ? Hbuf[1][wi * 16 + lq + 4 * r][wj * 16 + l16] : 0.0);
         }
     }
     // prefetch the first chunk of the rotation phase; it lands during the inner solve
@@ -255,14 +260,15 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
     if (!any_rot) return;
     if (tid == 0) rot[sweep] = 1;
 
-    // ---- inner cyclic Jacobi on the 32 x 32 Gram matrix, parallel order.
-    // Thread t < 256, (pi_, pj_) = (t / 16, t % 16), owns the 2 x 2 block
-    // (pair pi_ rows) x (pair pj_ cols) of H; thread 256 + t owns the 2 x 2
-    // block (pair pi_ rows) x (columns 2 pj_, 2 pj_ + 1) of P, so the two
-    // updates run side by side.  H is double-buffered so one barrier per step
-    // suffices.
-    const bool on_h = tid < 256;
-    const int pr_i = (tid & 255) >> 4, pr_j = tid & 15;
+    // ---- inner cyclic Jacobi on the JR x JR Gram matrix, parallel order.
+    // Thread t (mod JHB), (pi_, pj_) = (t / JNP, t % JNP), owns the 2 x 2 block
+    // (pair pi_ rows) x (pair pj_ cols) of H and/or the 2 x 2 block (pair pi_
+    // rows) x (columns 2 pj_, 2 pj_ + 1) of P: with 2 JHB <= 1024 threads the
+    // two updates run side by side on separate threads.  H is double-buffered
+    // so one barrier per step suffices.
+    const bool on_h = !JSPLIT || tid < JHB;
+    const bool on_p = !JSPLIT || tid >= JHB;
+    const int pr_i = (tid % JHB) / JNP, pr_j = tid % JNP;
     int cur = 0;
     for (int isw = 0; isw < JAC_INNER_SWEEPS; ++isw) {
         for (int step = 0; step < JR - 1; ++step) {
@@ -282,7 +288,8 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
                 Hn[p_i][q_j] = t00 * sj + t01 * cj;
                 Hn[q_i][p_j] = t10 * cj - t11 * sj;
                 Hn[q_i][q_j] = t10 * sj + t11 * cj;
-            } else if (si != 0.0) {
+            }
+            if (on_p && si != 0.0) {
                 const int c0 = 2 * pr_j, c1 = 2 * pr_j + 1;
                 const double x0 = Ps[p_i][c0], x1 = Ps[p_i][c1], y0 = Ps[q_i][c0], y1 = Ps[q_i][c1];
                 Ps[p_i][c0] = ci * x0 - si * y0;

@@ -1363,7 +1363,7 @@ int rsvd_plan_profile(rsvd_plan_t* plan, const void* const* A, void* const* U, v
         std::vector<int> st(2);
         for (const ProbHost& h : plan->probs) {
             HIPCHK(hipMemcpy(st.data(), plan->ws + h.o_stats, 2 * sizeof(int), hipMemcpyDeviceToHost));
-            flops[RSVD_PHASE_JACOBI] += 2.0 * 32 * 32 * h.C * st[0] + 2.0 * 32 * 32 * ((double)h.C + h.R) * st[1];
+            flops[RSVD_PHASE_JACOBI] += 2.0 * (2 * JAC_B) * (2 * JAC_B) * (h.C * (double)st[0] + ((double)h.C + h.R) * st[1]);
         }
     }
     return RSVD_OK;
