@@ -269,6 +269,7 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
     const bool on_h = !JSPLIT || tid < JHB;
     const bool on_p = !JSPLIT || tid >= JHB;
     const int pr_i = (tid % JHB) / JNP, pr_j = tid % JNP;
+    static_assert(JNP <= 64 && 64 % JNP == 0, "every wave computes all plane-pair rotations");
     int cur = 0;
     for (int isw = 0; isw < JAC_INNER_SWEEPS; ++isw) {
         for (int step = 0; step < JR - 1; ++step) {
@@ -276,11 +277,13 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
             const int p_j = rr_block(pr_j, step, JR), q_j = rr_block(JR - 1 - pr_j, step, JR);
             double (*H)[JR + 1] = Hbuf[cur];
             double (*Hn)[JR + 1] = Hbuf[cur ^ 1];
-            double ci, si;
-            jac_rotation(H[p_i][p_i], H[q_i][q_i], H[p_i][q_i], tol, ci, si);
+            // each lane computes the rotation of plane pair pr_j (= lane % JNP,
+            // so every wave holds all JNP of them) and takes pair pr_i's from
+            // the lane that computed it: one rotation per thread, not two
+            double cj, sj;
+            jac_rotation(H[p_j][p_j], H[q_j][q_j], H[p_j][q_j], tol, cj, sj);
+            const double ci = __shfl(cj, pr_i, 64), si = __shfl(sj, pr_i, 64);
             if (on_h) {
-                double cj, sj;
-                jac_rotation(H[p_j][p_j], H[q_j][q_j], H[p_j][q_j], tol, cj, sj);
                 const double b00 = H[p_i][p_j], b01 = H[p_i][q_j], b10 = H[q_i][p_j], b11 = H[q_i][q_j];
                 const double t00 = ci * b00 - si * b10, t01 = ci * b01 - si * b11;
                 const double t10 = si * b00 + ci * b10, t11 = si * b01 + ci * b11;
