@@ -319,36 +319,48 @@ hipError_t launch_jacobi_round(const JacDesc* d, const int* pair_begin, int npro
 }
 
 // ---------------------------------------------------------------- finishing
+// The finishing step is split so that only the O(R^2) rank sort and the
+// serial discarded-weight scan run in one workgroup per problem; the row norms
+// before it and the gathers of the singular vectors after it are wide,
+// coalesced launches over (problem, row group) work items.
 constexpr int FIN_MAXR = 2048;
 
+// sig[i] = ||X row i|| for the R rows of every problem (unsorted); one wave per row.
+__global__ __launch_bounds__(256) void rownorm_kernel(const FinDesc* __restrict__ descs,
+                                                      const int* __restrict__ map, int nprob)
+{
+    const int2 wi_ = wg_item(map, blockIdx.x);
+    const FinDesc& d = descs[wi_.x];
+    const int lane = threadIdx.x & 63, i = 4 * wi_.y + (threadIdx.x >> 6);
+    if (i >= d.R) return;
+    const int C = d.C;
+    const GLB double* __restrict__ X = to_glb(d.X) + (int64_t)i * d.ldx;
+    double s = 0.0;
+    for (int t0 = lane; t0 < C; t0 += 64 * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0 + 64 * u;
+            v[u] = ld_or0(X, t, t < C);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s = fma(v[u], v[u], s);
+    }
+    s = wave_sum(s);
+    if (lane == 0) to_glb(d.sig)[i] = sqrt(s);
+}
+
+// Rank sort of the row norms, truncation rule, discarded weight, status and S.
 template <typename TO>
 __global__ __launch_bounds__(256) void finish_kernel(const FinDesc* __restrict__ descs)
 {
     __shared__ double sig[FIN_MAXR];
     __shared__ double tail[FIN_MAXR + 1];
     __shared__ int perm_s[FIN_MAXR];
-    __shared__ int kk_s;
     const FinDesc& d = descs[blockIdx.x];
-    const int R = d.R, C = d.C;
-    const GLB double* __restrict__ X = to_glb(d.X);
-    const GLB double* __restrict__ Pm = to_glb(d.P);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-    for (int i = wave; i < R; i += 4) {
-        double s = 0.0;
-        for (int t0 = lane; t0 < C; t0 += 64 * 8) {
-            double v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int t = t0 + 64 * u;
-                v[u] = ld_or0(X, (int64_t)i * d.ldx + t, t < C);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) s = fma(v[u], v[u], s);
-        }
-        s = wave_sum(s);
-        if (lane == 0) sig[i] = sqrt(s);
-    }
+    const int R = d.R;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < R; i += 256) sig[i] = to_glb(d.sig)[i];
     __syncthreads();
     // Stable descending rank sort on a total order: NaN (only from non-finite
     // input) sorts last and equal keys keep index order, so the ranks always
@@ -367,6 +379,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinDesc* __restrict__
         to_glb(d.sig)[j] = sig[perm_s[j]];
         to_glb(d.perm)[j] = perm_s[j];
     }
+    __shared__ int kk_s;
     if (tid == 0) {
         const double normA2 = *to_glb(d.normA2);
         const int k = d.k;
@@ -424,146 +437,211 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinDesc* __restrict__
     }
     __syncthreads();
     const int kk = kk_s;
-    const int k = d.k;
     GLB TO* __restrict__ S = (GLB TO*)d.S;
-    GLB TO* __restrict__ U = (GLB TO*)d.U;
-    GLB TO* __restrict__ VT = (GLB TO*)d.VT;
-    for (int j = tid; j < k; j += 256) S[j] = (j < kk) ? (TO)sig[perm_s[j]] : (TO)0;
-    const int n = d.n, m = d.m;
-    // right vectors (rows of VT) and, for the full SVD, left vectors: a flat
-    // index space over (j, t) with 8 loads in flight per thread
-    const int64_t nv = (int64_t)k * n;
-    for (int64_t base = tid; base < nv; base += 256 * 8) {
+    for (int j = tid; j < d.k; j += 256) S[j] = (j < kk) ? (TO)sig[perm_s[j]] : (TO)0;
+}
+
+// Source of output vector j: row perm[j] of X scaled by 1/sigma_j (a column of
+// X^T divided by its norm), or row perm[j] of the accumulated rotation P.
+struct VecSrc {
+    const GLB double* base;
+    int64_t ld;
+    bool scaled;
+};
+__device__ __forceinline__ VecSrc vec_src(const FinDesc& d, bool from_p)
+{
+    return from_p ? VecSrc{to_glb(d.P), d.ldp, false} : VecSrc{to_glb(d.X), d.ldx, true};
+}
+
+// Rows j of VT (zero for j >= k_kept): one wave per row, coalesced over the row.
+template <typename TO>
+__global__ __launch_bounds__(256) void gather_vt_kernel(const FinDesc* __restrict__ descs,
+                                                        const int* __restrict__ map, int nprob)
+{
+    const int2 wi_ = wg_item(map, blockIdx.x);
+    const FinDesc& d = descs[wi_.x];
+    const int lane = threadIdx.x & 63, j = 4 * wi_.y + (threadIdx.x >> 6);
+    if (j >= d.k) return;
+    const int n = d.n;
+    const bool keep = j < *to_glb(d.kkept_out);
+    const VecSrc vs = vec_src(d, d.mode == 2);
+    const int src = to_glb(d.perm)[keep ? j : 0];
+    const double sj = to_glb(d.sig)[keep ? j : 0];
+    const double scale = !keep ? 0.0 : (!vs.scaled ? 1.0 : (sj > 0.0 ? 1.0 / sj : 0.0));
+    const GLB double* __restrict__ row = vs.base + (int64_t)src * vs.ld;
+    GLB TO* __restrict__ out = (GLB TO*)d.VT + (int64_t)j * d.ldvt;
+    for (int t0 = lane; t0 < n; t0 += 64 * 8) {
         double v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int64_t e = base + 256 * u;
-            v[u] = 0.0;
-            if (e < nv) {
-                const int j = (int)(e / n), t = (int)(e % n);
-                if (j < kk) {
-                    const int src = perm_s[j];
-                    if (d.mode == 2) {
-                        v[u] = Pm[(int64_t)src * d.ldp + t];
-                    } else {
-                        const double sj = sig[src];
-                        v[u] = X[(int64_t)src * d.ldx + t] * (sj > 0.0 ? 1.0 / sj : 0.0);
-                    }
-                }
-            }
+            const int t = t0 + 64 * u;
+            v[u] = ld_or0(row, t, keep && t < n);
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int64_t e = base + 256 * u;
-            if (e < nv) VT[(e / n) * d.ldvt + e % n] = (TO)v[u];
-        }
-    }
-    if (d.mode == 1 || d.mode == 2) {
-        const int64_t nu = (int64_t)k * m;
-        for (int64_t base = tid; base < nu; base += 256 * 8) {
-            double v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int64_t e = base + 256 * u;
-                v[u] = 0.0;
-                if (e < nu) {
-                    const int j = (int)(e / m), i = (int)(e % m);
-                    if (j < kk) {
-                        const int src = perm_s[j];
-                        if (d.mode == 1) {
-                            v[u] = Pm[(int64_t)src * d.ldp + i];
-                        } else {
-                            const double sj = sig[src];
-                            v[u] = X[(int64_t)src * d.ldx + i] * (sj > 0.0 ? 1.0 / sj : 0.0);
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int64_t e = base + 256 * u;
-                if (e < nu) U[(e % m) * d.ldu + e / m] = (TO)v[u];
-            }
+            const int t = t0 + 64 * u;
+            if (t < n) out[t] = (TO)(v[u] * scale);
         }
     }
 }
 
-hipError_t launch_finish(const FinDesc* d, int nprob, int out_f64, hipStream_t s)
+// Columns j of U for the full SVD, through a 64 x 64 LDS transpose so that
+// both the reads (rows of the source) and the writes (rows of U) are coalesced.
+template <typename TO>
+__global__ __launch_bounds__(256) void gather_u_kernel(const FinDesc* __restrict__ descs,
+                                                       const int* __restrict__ map, int nprob)
+{
+    __shared__ double tile[64][65];
+    const int2 wi_ = wg_item(map, blockIdx.x);
+    const FinDesc& d = descs[wi_.x];
+    const int m = d.m, k = d.k;
+    const int tiles_j = (k + 63) / 64;
+    const int j0 = 64 * (wi_.y % tiles_j), i0 = 64 * (wi_.y / tiles_j);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kk = (int)*to_glb(d.kkept_out);
+    const VecSrc vs = vec_src(d, d.mode == 1);
+    const int i = i0 + lane;
+#pragma unroll 4
+    for (int r = 0; r < 16; ++r) {
+        const int jj = wave + 4 * r, j = j0 + jj;
+        const bool keep = j < kk;
+        const int src = to_glb(d.perm)[keep ? j : 0];
+        const double sj = to_glb(d.sig)[keep ? j : 0];
+        const double scale = !keep ? 0.0 : (!vs.scaled ? 1.0 : (sj > 0.0 ? 1.0 / sj : 0.0));
+        tile[jj][lane] = ld_or0(vs.base, (int64_t)src * vs.ld + i, keep && i < m) * scale;
+    }
+    __syncthreads();
+    const int j = j0 + lane;
+    GLB TO* __restrict__ U = (GLB TO*)d.U;
+#pragma unroll 4
+    for (int r = 0; r < 16; ++r) {
+        const int ii = wave + 4 * r;
+        if (i0 + ii < m && j < k) U[(int64_t)(i0 + ii) * d.ldu + j] = (TO)tile[lane][ii];
+    }
+}
+
+hipError_t launch_finish(const FinDesc* d, int nprob, const int* norm_map, int norm_total, const int* vt_map,
+                         int vt_total, const int* u_map, int u_total, int out_f64, hipStream_t s)
 {
     if (nprob <= 0) return hipSuccess;
-    if (out_f64)
+    if (norm_total > 0) hipLaunchKernelGGL(rownorm_kernel, dim3(norm_total), dim3(256), 0, s, d, norm_map, nprob);
+    if (out_f64) {
         hipLaunchKernelGGL(finish_kernel<double>, dim3(nprob), dim3(256), 0, s, d);
-    else
+        if (vt_total > 0)
+            hipLaunchKernelGGL(gather_vt_kernel<double>, dim3(vt_total), dim3(256), 0, s, d, vt_map, nprob);
+        if (u_total > 0)
+            hipLaunchKernelGGL(gather_u_kernel<double>, dim3(u_total), dim3(256), 0, s, d, u_map, nprob);
+    } else {
         hipLaunchKernelGGL(finish_kernel<float>, dim3(nprob), dim3(256), 0, s, d);
+        if (vt_total > 0)
+            hipLaunchKernelGGL(gather_vt_kernel<float>, dim3(vt_total), dim3(256), 0, s, d, vt_map, nprob);
+        if (u_total > 0)
+            hipLaunchKernelGGL(gather_u_kernel<float>, dim3(u_total), dim3(256), 0, s, d, u_map, nprob);
+    }
     return hipGetLastError();
 }
 
+// Canonical signs: for 64 columns of U per workgroup (lane = column, so every
+// access is a coalesced row segment), find the entry of largest magnitude
+// (lowest row on ties, NaN never chosen), make it positive by flipping the
+// column of U and the matching row of VT, and zero the columns >= k_kept.
+constexpr int SF_WAVES = 16;
 template <typename TO>
-__global__ __launch_bounds__(64) void signfix_kernel(const FinDesc* __restrict__ descs,
-                                                     const int* __restrict__ col_begin, int nprob)
+__global__ __launch_bounds__(64 * SF_WAVES) void signfix_kernel(const FinDesc* __restrict__ descs,
+                                                                const int* __restrict__ map, int nprob)
 {
-    const int t = blockIdx.x;
-    const int2 wi_ = wg_item(col_begin, t);
-    const int b = wi_.x;
-    const FinDesc& d = descs[b];
-    const int j = wi_.y;
-    const int lane = threadIdx.x;
-    const int64_t kk = *to_glb(d.kkept_out);
+    __shared__ double best_s[SF_WAVES][64];
+    __shared__ int idx_s[SF_WAVES][64];
+    __shared__ int flip_s[64];
+    const int2 wi_ = wg_item(map, blockIdx.x);
+    const FinDesc& d = descs[wi_.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = d.m, n = d.n, k = d.k;
+    const int j0 = 64 * wi_.y, j = j0 + lane;
+    const int kk = (int)*to_glb(d.kkept_out);
+    const bool col = j < k, kept = j < kk;
     GLB TO* __restrict__ U = (GLB TO*)d.U;
     GLB TO* __restrict__ VT = (GLB TO*)d.VT;
-    const int m = d.m, n = d.n;
-    GLB double* __restrict__ sgn = to_glb(d.sgn);
-    if (j >= kk) {
-        for (int i = lane; i < m; i += 64) U[(int64_t)i * d.ldu + j] = (TO)0;
-        if (sgn && lane == 0) sgn[j] = 0.0;
-        return;
-    }
     double best = -1.0;
     int bi = 0x7fffffff;
-    for (int i0 = lane; i0 < m; i0 += 64 * 8) {
+    for (int i0 = wave; i0 < m; i0 += SF_WAVES * 8) {
         double v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int i = i0 + 64 * u;
-            v[u] = (i < m) ? fabs((double)U[(int64_t)i * d.ldu + j]) : -1.0;
+            const int i = i0 + SF_WAVES * u;
+            const bool ok = kept && i < m;
+            v[u] = ok ? fabs((double)ld_or0((const GLB TO*)U, (int64_t)i * d.ldu + j, ok)) : -1.0;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             if (v[u] > best) {
                 best = v[u];
-                bi = i0 + 64 * u;
+                bi = i0 + SF_WAVES * u;
             }
         }
     }
+    best_s[wave][lane] = best;
+    idx_s[wave][lane] = bi;
+    __syncthreads();
+    if (wave == 0) {
+        for (int w = 1; w < SF_WAVES; ++w) {
+            const double ob = best_s[w][lane];
+            const int oi = idx_s[w][lane];
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        // no finite entry: the column is left as it is
+        const bool flip = kept && bi < m && (double)U[(int64_t)(bi < m ? bi : 0) * d.ldu + j] < 0.0;
+        flip_s[lane] = flip;
+        GLB double* __restrict__ sgn = to_glb(d.sgn);
+        if (sgn && col) sgn[j] = !kept ? 0.0 : (flip ? -1.0 : 1.0);
+    }
+    __syncthreads();
+    const bool flip = flip_s[lane];
+    if (col && (flip || !kept)) {
+        for (int i0 = wave; i0 < m; i0 += SF_WAVES * 8) {
+            TO v[8];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-            best = ob;
-            bi = oi;
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + SF_WAVES * u;
+                v[u] = ld_or0((const GLB TO*)U, (int64_t)i * d.ldu + j, kept && i < m);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + SF_WAVES * u;
+                if (i < m) U[(int64_t)i * d.ldu + j] = kept ? -v[u] : (TO)0;
+            }
         }
     }
-    if (bi >= m) {  // no finite entry: leave the column as it is
-        if (sgn && lane == 0) sgn[j] = 1.0;
-        return;
-    }
-    const bool flip = (double)U[(int64_t)bi * d.ldu + j] < 0.0;
-    if (sgn && lane == 0) sgn[j] = flip ? -1.0 : 1.0;
-    if (flip) {
-        for (int i = lane; i < m; i += 64) U[(int64_t)i * d.ldu + j] = -U[(int64_t)i * d.ldu + j];
-        for (int x = lane; x < n; x += 64) VT[(int64_t)j * d.ldvt + x] = -VT[(int64_t)j * d.ldvt + x];
+    // rows of VT: wave w takes rows j0 + w, j0 + w + SF_WAVES, ...
+    for (int r = wave; r < 64; r += SF_WAVES) {
+        if (!flip_s[r] || j0 + r >= k) continue;
+        GLB TO* __restrict__ vrow = VT + (int64_t)(j0 + r) * d.ldvt;
+        for (int x0 = lane; x0 < n; x0 += 64 * 8) {
+            TO v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int x = x0 + 64 * u;
+                v[u] = ld_or0((const GLB TO*)vrow, x, x < n);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int x = x0 + 64 * u;
+                if (x < n) vrow[x] = -v[u];
+            }
+        }
     }
 }
 
-hipError_t launch_signfix(const FinDesc* d, const int* col_begin, int nprob, int total_cols, int out_f64,
-                          hipStream_t s)
+hipError_t launch_signfix(const FinDesc* d, const int* map, int nprob, int total, int out_f64, hipStream_t s)
 {
-    if (total_cols <= 0) return hipSuccess;
+    if (total <= 0) return hipSuccess;
     if (out_f64)
-        hipLaunchKernelGGL(signfix_kernel<double>, dim3(total_cols), dim3(64), 0, s, d, col_begin, nprob);
+        hipLaunchKernelGGL(signfix_kernel<double>, dim3(total), dim3(64 * SF_WAVES), 0, s, d, map, nprob);
     else
-        hipLaunchKernelGGL(signfix_kernel<float>, dim3(total_cols), dim3(64), 0, s, d, col_begin, nprob);
+        hipLaunchKernelGGL(signfix_kernel<float>, dim3(total), dim3(64 * SF_WAVES), 0, s, d, map, nprob);
     return hipGetLastError();
 }
 

@@ -129,11 +129,15 @@ struct FinDesc {
     int pad_;
     double delta;
 };
-hipError_t launch_finish(const FinDesc* d, int nprob, int out_f64, hipStream_t s);
+// Row norms (item map over groups of 4 rows of X), rank sort and truncation
+// (one workgroup per problem), then the gathers of VT (item map over groups of
+// 4 rows of VT) and, for the full SVD, of U (item map over 64 x 64 tiles of U).
+hipError_t launch_finish(const FinDesc* d, int nprob, const int* norm_map, int norm_total, const int* vt_map,
+                         int vt_total, const int* u_map, int u_total, int out_f64, hipStream_t s);
 // Zero columns >= k_kept of U and make the largest-magnitude entry of every kept
-// left vector positive (flipping the matching row of VT).  col_begin: item map over k columns.
-hipError_t launch_signfix(const FinDesc* d, const int* col_begin, int nprob, int total_cols,
-                          int out_f64, hipStream_t s);
+// left vector positive (flipping the matching row of VT).  map: item map over
+// groups of 64 columns.
+hipError_t launch_signfix(const FinDesc* d, const int* map, int nprob, int total, int out_f64, hipStream_t s);
 
 // ---------------------------------------------------------------- staging
 // ||A||_F^2 (deterministic two-level FP64 reduction) and optional cast of A.

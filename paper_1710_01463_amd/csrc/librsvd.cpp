@@ -154,7 +154,7 @@ struct rsvd_plan {
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
     // recorded launch layout (offsets into the blob)
-    IdxLaunch stage, omega, copy, eye, finish, signfix;
+    IdxLaunch stage, omega, copy, eye, finish, fin_norm, fin_vt, fin_u, signfix;
     std::vector<GemmLaunch> g_sketch, g_gram1, g_gram2;
     std::vector<IdxLaunch> qr, trsm;
     GemmLaunch g_b, g_u;
@@ -606,7 +606,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
     // finish + sign fix
     {
         std::vector<FinDesc> d(np);
-        std::vector<int> ones(np, 1), cols(np);
+        std::vector<int> ones(np, 1), cols(np), rows4(np), vt4(np), utiles(np);
         for (int b = 0; b < np; ++b) {
             const ProbHost& h = P.probs[b];
             FinDesc& f = d[b];
@@ -636,9 +636,15 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             f.mode = h.mode;
             f.max_sweeps = P.max_sweeps;
             f.delta = h.delta;
-            cols[b] = (int)h.k;
+            rows4[b] = (h.R + 3) / 4;
+            vt4[b] = (int)((h.k + 3) / 4);
+            utiles[b] = h.mode == 0 ? 0 : (int)(((h.k + 63) / 64) * ((h.m + 63) / 64));
+            cols[b] = (int)((h.k + 63) / 64);
         }
         P.finish = add_idx(B, d, ones);
+        P.fin_norm = add_idx(B, d, rows4);
+        P.fin_vt = add_idx(B, d, vt4);
+        P.fin_u = add_idx(B, d, utiles);
         P.signfix = add_idx(B, d, cols);
     }
     if (!P.fullsvd) {
@@ -728,7 +734,10 @@ int enqueue(rsvd_plan& P, hipStream_t s)
             PLAUNCH(RSVD_PHASE_JACOBI, 0.0,
                     launch_jacobi_round(dp<JacDesc>(P, P.jac.off_desc), dp<int>(P, P.jac.off_begin), np, P.jac.total,
                                         sw, r, s));
-    PLAUNCH(RSVD_PHASE_FINISH, 0.0, launch_finish(dp<FinDesc>(P, P.finish.off_desc), np, out_f64, s));
+    PLAUNCH(RSVD_PHASE_FINISH, 0.0,
+            launch_finish(dp<FinDesc>(P, P.finish.off_desc), np, dp<int>(P, P.fin_norm.off_begin), P.fin_norm.total,
+                          dp<int>(P, P.fin_vt.off_begin), P.fin_vt.total, dp<int>(P, P.fin_u.off_begin), P.fin_u.total,
+                          out_f64, s));
     if (!P.fullsvd) {
         if ((rc = gemm(P, P.g_u, s, RSVD_PHASE_BACKPROJ)) != RSVD_OK) return rc;
     }
