@@ -173,9 +173,16 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
     if (round >= nb - 1) return;
     GLB int* __restrict__ rot = to_glb(d.rot);
     if (sweep > 0 && rot[sweep - 1] == 0) return;
-    const int pi = wi_.y;
-    const int I = rr_block(pi, round, nb);
-    const int J = rr_block(nb - 1 - pi, round, nb);
+    // With an odd number of row blocks, the padding block (nb - 1) takes the
+    // fixed position 0 of the round-robin schedule, so that its pair is always
+    // slot 0: that slot is not launched (the other blocks sit out once per sweep).
+    const int pi = wi_.y + d.skip0;
+    int I = rr_block(pi, round, nb);
+    int J = rr_block(nb - 1 - pi, round, nb);
+    if (d.skip0) {
+        I = I == 0 ? nb - 1 : I - 1;
+        J = J == 0 ? nb - 1 : J - 1;
+    }
     const int R = d.R, C = d.C;
     const double tol = d.tol;
     GLB double* __restrict__ X = to_glb(d.X);

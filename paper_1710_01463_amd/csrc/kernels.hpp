@@ -97,7 +97,7 @@ struct JacDesc {
     int* stats;        // [0] block pairs whose Gram was formed, [1] rotations applied
     int64_t ldx, ldp;
     int R, C, nb;
-    int pad_;
+    int skip0;         // 1: block nb - 1 is all padding and its pair is not launched
     double tol;
 };
 constexpr int JAC_B = 16;

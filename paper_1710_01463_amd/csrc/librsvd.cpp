@@ -597,8 +597,10 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             j.R = h.R;
             j.C = h.C;
             j.nb = h.nb;
+            // odd block count (last block all padding) with at least 3 real blocks
+            j.skip0 = (h.nb >= 4 && (h.nb - 1) * JAC_B >= h.R) ? 1 : 0;
             j.tol = (double)h.C * std::ldexp(1.0, -53);
-            cj[b] = h.nb / 2;
+            cj[b] = h.nb / 2 - j.skip0;
         }
         P.eye = add_idx(B, de, ce);
         P.jac = add_idx(B, dj, cj);
