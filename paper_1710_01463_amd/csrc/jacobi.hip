@@ -23,7 +23,7 @@ constexpr int JNP = JR / 2;                      // plane pairs per inner step
 constexpr int JHB = JNP * JNP;                   // 2 x 2 blocks of the pair's Gram
 constexpr int JT = (2 * JHB <= 1024) ? 2 * JHB : JHB;  // threads per workgroup
 constexpr bool JSPLIT = JT == 2 * JHB;           // separate threads update P
-constexpr int JCH = JR >= 64 ? 64 : 128;         // column chunk staged through LDS
+constexpr int JCH = JR >= 64 ? 64 : JAC_CHUNK;   // column chunk staged through LDS
 constexpr int JPF = JR * JCH / JT;               // prefetched doubles per thread
 constexpr int JTILES = (JR / 16) * (JR / 16);    // 16 x 16 Gram tiles
 constexpr int JKS = (JT / 64) / JTILES;          // waves sharing one Gram tile (k split)
@@ -155,6 +155,49 @@ __device__ void apply_rotation(const ChunkSeq& cs, double (&pre)[JPF], const int
 
 constexpr int JAC_INNER_SWEEPS = 1;
 
+// rows <- Ps * rows for chunks already held in registers (res[ch] = chunk ch of
+// the sequence): no global load on the way, only the LDS transpose for MFMA.
+template <int NS>
+__device__ void apply_rotation_resident(const ChunkSeq& cs, double (&res)[NS][JPF], int ch0, int ch_end,
+                                        const int* rowmap, double (*Ps)[JR + 1], double (*Xs)[JCH + 1])
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+        const int ci = ch0 + sl;
+        if (ci >= ch_end) break;  // uniform; no load below
+        store_chunk(res[sl], Xs);
+        __syncthreads();
+        GLB double* M;
+        int64_t ldm;
+        int ncols, c0;
+        cs.select(ci, M, ldm, ncols, c0);
+        for (int tl = wave; tl < (JR / 16) * (JCH / 16); tl += JT / 64) {
+            const int rt = tl / (JCH / 16), tj = tl % (JCH / 16);
+            dbl4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int kk = 0; kk < JR; kk += 4)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ps[rt * 16 + l16][kk + lq], Xs[kk + lq][tj * 16 + l16], acc,
+                                                           0, 0, 0);
+            const int gc = c0 + tj * 16 + l16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int g = rowmap[rt * 16 + lq + 4 * r];
+                if (gc < ncols && g >= 0) M[(int64_t)g * ldm + gc] = acc[r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One round of the block Jacobi schedule.  RX > 0: the pair's rows of X
+// (at most RX column chunks) are loaded into registers at once at the start
+// and reused for the rotation, and the rows of P (at most RP chunks) are
+// loaded during the inner solve, so that the global-memory latency is paid
+// about twice per round instead of once per chunk.  RX = 0: chunks are
+// streamed through a one-deep register prefetch (any C and R).
+template <int RX, int RP>
 __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restrict__ descs,
                                                            const int* __restrict__ pair_begin, int nprob,
                                                            int sweep, int round)
@@ -195,28 +238,57 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
         rowmap[tid] = (gr < R) ? gr : -1;
     }
     if (tid == 0) any_rot = 0;
+    ChunkSeq seq;
+    seq.X = X;
+    seq.P = to_glb(d.P);
+    seq.ldx = ldx;
+    seq.ldp = d.ldp;
+    seq.C = C;
+    seq.R = R;
+    seq.ncx = (C + JCH - 1) / JCH;
+    seq.nct = seq.ncx + (d.P ? (R + JCH - 1) / JCH : 0);
     __syncthreads();
 
     // ---- Gram matrix of the JR rows (FP64 MFMA): wave w forms the 16 x 16
     // tile (w % JTILES) over its share (w / JTILES of JKS) of every column
     // chunk; with JKS = 2 the two halves are added through LDS
+    constexpr int NRX = RX > 0 ? RX : 1;
+    double resx[NRX][JPF];
     {
         const int tile = wave % JTILES;
         const int wi = tile / (JR / 16), wj = tile % (JR / 16), half = wave / JTILES;
         dbl4 acc = {0, 0, 0, 0};
-        double pre[JPF];
-        load_chunk(pre, X, ldx, C, 0, rowmap);
-        for (int c0 = 0; c0 < C; c0 += JCH) {
-            store_chunk(pre, Xs);
-            __syncthreads();
-            if (c0 + JCH < C) load_chunk(pre, X, ldx, C, c0 + JCH, rowmap);
+        auto gram_chunk = [&]() {
 #pragma unroll 8
             for (int kk = half * (JCH / JKS); kk < (half + 1) * (JCH / JKS); kk += 4) {
                 const double av = Xs[wi * 16 + l16][kk + lq];
                 const double bv = Xs[wj * 16 + l16][kk + lq];
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
             }
-            __syncthreads();
+        };
+        if constexpr (RX > 0) {
+            // every X chunk in flight at once (slots past the row length
+            // re-read chunk 0 and are not used)
+#pragma unroll
+            for (int ch = 0; ch < RX; ++ch) load_chunk(resx[ch], X, ldx, C, (ch < seq.ncx ? ch : 0) * JCH, rowmap);
+#pragma unroll
+            for (int ch = 0; ch < RX; ++ch) {
+                if (ch > 0 && ch >= seq.ncx) break;  // uniform; no load below
+                store_chunk(resx[ch], Xs);
+                __syncthreads();
+                gram_chunk();
+                __syncthreads();
+            }
+        } else {
+            double pre[JPF];
+            load_chunk(pre, X, ldx, C, 0, rowmap);
+            for (int c0 = 0; c0 < C; c0 += JCH) {
+                store_chunk(pre, Xs);
+                __syncthreads();
+                if (c0 + JCH < C) load_chunk(pre, X, ldx, C, c0 + JCH, rowmap);
+                gram_chunk();
+                __syncthreads();
+            }
         }
         static_assert(JKS <= 2, "Gram halves");
         if (JKS == 2 && half == 1) {
@@ -231,18 +303,9 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
                     acc[r] + (JKS == 2 ? Hbuf[1][wi * 16 + lq + 4 * r][wj * 16 + l16] : 0.0);
         }
     }
-    // prefetch the first chunk of the rotation phase; it lands during the inner solve
-    ChunkSeq seq;
-    seq.X = X;
-    seq.P = to_glb(d.P);
-    seq.ldx = ldx;
-    seq.ldp = d.ldp;
-    seq.C = C;
-    seq.R = R;
-    seq.ncx = (C + JCH - 1) / JCH;
-    seq.nct = seq.ncx + (d.P ? (R + JCH - 1) / JCH : 0);
+    // streaming: prefetch the first chunk of the rotation phase; it lands during the inner solve
     double pre[JPF];
-    seq.load(pre, 0, rowmap);
+    if constexpr (RX == 0) seq.load(pre, 0, rowmap);
     __syncthreads();
     // symmetrise from the upper triangle, identity for P
     for (int e = tid; e < JR * JR; e += JT) {
@@ -266,6 +329,16 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
     }
     if (!any_rot) return;
     if (tid == 0) rot[sweep] = 1;
+    // resident: the rows of P, in flight during the inner solve
+    constexpr int NRP = RP > 0 ? RP : 1;
+    double resp[NRP][JPF];
+    if constexpr (RX > 0) {
+#pragma unroll
+        for (int sl = 0; sl < RP; ++sl) {
+            const int ci = seq.ncx + sl;
+            seq.load(resp[sl], ci < seq.nct ? ci : 0, rowmap);
+        }
+    }
 
     // ---- inner cyclic Jacobi on the JR x JR Gram matrix, parallel order.
     // Thread t (mod JHB), (pi_, pj_) = (t / JNP, t % JNP), owns the 2 x 2 block
@@ -313,15 +386,43 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
     }
 
     // ---- apply the accumulated rotation to the rows of X and of P
-    apply_rotation(seq, pre, rowmap, Ps, Xs);
+    if constexpr (RX > 0) {
+        apply_rotation_resident<RX>(seq, resx, 0, seq.ncx, rowmap, Ps, Xs);
+        apply_rotation_resident<RP>(seq, resp, seq.ncx, seq.nct, rowmap, Ps, Xs);
+    } else {
+        apply_rotation(seq, pre, rowmap, Ps, Xs);
+    }
+}
+
+int jacobi_resident_variant(int max_x_chunks, int max_p_chunks)
+{
+    if (max_x_chunks <= 4 && max_p_chunks <= 3) return 1;
+    if (max_x_chunks <= 4 && max_p_chunks <= 4) return 2;
+    if (max_x_chunks <= 8 && max_p_chunks <= 2) return 3;
+    return 0;
 }
 
 hipError_t launch_jacobi_round(const JacDesc* d, const int* pair_begin, int nprob, int total_pairs,
-                               int sweep, int round, hipStream_t s)
+                               int sweep, int round, int variant, hipStream_t s)
 {
     if (total_pairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(jacobi_round_kernel, dim3(total_pairs), dim3(JT), 0, s, d, pair_begin, nprob,
-                       sweep, round);
+    switch (variant) {
+    case 1:
+        hipLaunchKernelGGL((jacobi_round_kernel<4, 3>), dim3(total_pairs), dim3(JT), 0, s, d, pair_begin, nprob, sweep,
+                           round);
+        break;
+    case 2:
+        hipLaunchKernelGGL((jacobi_round_kernel<4, 4>), dim3(total_pairs), dim3(JT), 0, s, d, pair_begin, nprob, sweep,
+                           round);
+        break;
+    case 3:
+        hipLaunchKernelGGL((jacobi_round_kernel<8, 2>), dim3(total_pairs), dim3(JT), 0, s, d, pair_begin, nprob, sweep,
+                           round);
+        break;
+    default:
+        hipLaunchKernelGGL((jacobi_round_kernel<0, 0>), dim3(total_pairs), dim3(JT), 0, s, d, pair_begin, nprob, sweep,
+                           round);
+    }
     return hipGetLastError();
 }
 

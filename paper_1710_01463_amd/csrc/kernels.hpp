@@ -101,8 +101,14 @@ struct JacDesc {
     double tol;
 };
 constexpr int JAC_B = 16;
+// variant: 0 streams the column chunks of every pair (any size); k > 0 keeps
+// the pair's rows in registers, for problems whose row lengths fit the
+// variant (jacobi_resident_variant of the largest chunk counts, JAC_CHUNK
+// columns per chunk, X and P counted apart).
+constexpr int JAC_CHUNK = 128;
+int jacobi_resident_variant(int max_x_chunks, int max_p_chunks);
 hipError_t launch_jacobi_round(const JacDesc* d, const int* pair_begin, int nprob, int total_pairs,
-                               int sweep, int round, hipStream_t s);
+                               int sweep, int round, int variant, hipStream_t s);
 
 // ---------------------------------------------------------------- finishing
 // mode 0: RSVD (X = B rows, w from ||A||^2 - sum), mode 1: full SVD with X = A,

@@ -140,6 +140,7 @@ struct rsvd_plan {
     bool fullsvd = false;
     std::vector<ProbHost> probs;
     int max_l = 0, max_nb = 2, max_q = 0;
+    int jac_variant = 0;
     int max_sweeps = 20;
     Elem e_store = E_F64, e_sketch = E_F64, e_y = E_F64;
     bool need_cast = false;
@@ -604,6 +605,12 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
         }
         P.eye = add_idx(B, de, ce);
         P.jac = add_idx(B, dj, cj);
+        int mx = 0, mp = 0;
+        for (int b = 0; b < np; ++b) {
+            mx = std::max(mx, (P.probs[b].C + JAC_CHUNK - 1) / JAC_CHUNK);
+            mp = std::max(mp, (P.probs[b].R + JAC_CHUNK - 1) / JAC_CHUNK);
+        }
+        P.jac_variant = jacobi_resident_variant(mx, mp);
     }
     // finish + sign fix
     {
@@ -735,7 +742,7 @@ int enqueue(rsvd_plan& P, hipStream_t s)
         for (int r = 0; r < P.max_nb - 1; ++r)
             PLAUNCH(RSVD_PHASE_JACOBI, 0.0,
                     launch_jacobi_round(dp<JacDesc>(P, P.jac.off_desc), dp<int>(P, P.jac.off_begin), np, P.jac.total,
-                                        sw, r, s));
+                                        sw, r, P.jac_variant, s));
     PLAUNCH(RSVD_PHASE_FINISH, 0.0,
             launch_finish(dp<FinDesc>(P, P.finish.off_desc), np, dp<int>(P, P.fin_norm.off_begin), P.fin_norm.total,
                           dp<int>(P, P.fin_vt.off_begin), P.fin_vt.total, dp<int>(P, P.fin_u.off_begin), P.fin_u.total,
