@@ -10,9 +10,11 @@
 // takes one block pair (JR = 2 JAC_B rows), forms their JR x JR Gram matrix
 // with FP64 MFMA, checks the relative off-diagonal |h_ij| <= tol
 // sqrt(h_ii h_jj), and if needed diagonalises it by one sweep of cyclic
-// two-sided Jacobi in LDS, then applies the accumulated JR x JR rotation to
-// the JR rows of X and of P with FP64 MFMA.  A sweep is nb - 1 rounds; a problem is converged after a sweep in
-// which no block pair needed a rotation.
+// two-sided Jacobi in LDS (with many blocks, rounds 2.. of a sweep rotate only
+// the row pairs across the two blocks), then applies the accumulated JR x JR
+// rotation to the JR rows of X and of P with FP64 MFMA.  A sweep is nb - 1
+// rounds; a problem is converged after a sweep in which no off-diagonal entry
+// of any block pair was above the threshold.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -313,22 +315,27 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
         if (i > j) Hbuf[0][i][j] = Hbuf[0][j][i];
         Ps[i][j] = (i == j) ? 1.0 : 0.0;
     }
+    // cross round: only the row pairs across the two blocks are rotated (the
+    // pairs inside a block are visited in the full rounds 0 and 1)
+    const bool cross = d.cross_rounds && round >= 2;
     __syncthreads();
+    // any_rot bit 0: some off-diagonal entry above the threshold (the sweep
+    // has not converged); bit 1: some entry that this round rotates
     for (int e = tid; e < JR * JR; e += JT) {
         const int i = e / JR, j = e % JR;
         if (i < j) {
             const double a = Hbuf[0][i][i], c = Hbuf[0][j][j], g = Hbuf[0][i][j];
-            if (jac_needs(a, c, g, tol)) any_rot = 1;
+            if (jac_needs(a, c, g, tol)) atomicOr(&any_rot, (!cross || (i < JAC_B && j >= JAC_B)) ? 3 : 1);
         }
     }
     __syncthreads();
     if (tid == 0) {
         GLB int* st = to_glb(d.stats);
         atomicAdd((int*)&st[0], 1);
-        if (any_rot) atomicAdd((int*)&st[1], 1);
+        if (any_rot & 2) atomicAdd((int*)&st[1], 1);
+        if (any_rot) rot[sweep] = 1;
     }
-    if (!any_rot) return;
-    if (tid == 0) rot[sweep] = 1;
+    if (!(any_rot & 2)) return;
     // resident: the rows of P, in flight during the inner solve
     constexpr int NRP = RP > 0 ? RP : 1;
     double resp[NRP][JPF];
@@ -351,10 +358,15 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
     const int pr_i = (tid % JHB) / JNP, pr_j = tid % JNP;
     static_assert(JNP <= 64 && 64 % JNP == 0, "every wave computes all plane-pair rotations");
     int cur = 0;
+    const int nsteps = cross ? JAC_B : JR - 1;
     for (int isw = 0; isw < JAC_INNER_SWEEPS; ++isw) {
-        for (int step = 0; step < JR - 1; ++step) {
-            const int p_i = rr_block(pr_i, step, JR), q_i = rr_block(JR - 1 - pr_i, step, JR);
-            const int p_j = rr_block(pr_j, step, JR), q_j = rr_block(JR - 1 - pr_j, step, JR);
+        for (int step = 0; step < nsteps; ++step) {
+            // full: round-robin over all JR rows; cross: row p of block I with
+            // row JAC_B + (p + step) mod JAC_B of block J
+            const int p_i = cross ? pr_i : rr_block(pr_i, step, JR);
+            const int q_i = cross ? JAC_B + ((pr_i + step) & (JAC_B - 1)) : rr_block(JR - 1 - pr_i, step, JR);
+            const int p_j = cross ? pr_j : rr_block(pr_j, step, JR);
+            const int q_j = cross ? JAC_B + ((pr_j + step) & (JAC_B - 1)) : rr_block(JR - 1 - pr_j, step, JR);
             double (*H)[JR + 1] = Hbuf[cur];
             double (*Hn)[JR + 1] = Hbuf[cur ^ 1];
             // each lane computes the rotation of plane pair pr_j (= lane % JNP,

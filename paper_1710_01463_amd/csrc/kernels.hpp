@@ -98,6 +98,8 @@ struct JacDesc {
     int64_t ldx, ldp;
     int R, C, nb;
     int skip0;         // 1: block nb - 1 is all padding and its pair is not launched
+    int cross_rounds;  // 1: rounds >= 2 of a sweep rotate only the pairs across the two blocks
+    int pad_;
     double tol;
 };
 constexpr int JAC_B = 16;

@@ -45,6 +45,12 @@ constexpr int JAC_MAX_SWEEPS_RSVD = 14;
 constexpr int JAC_MAX_SWEEPS_RSVD_WIDE = 30;
 constexpr int JAC_WIDE_L = 272;
 constexpr int JAC_MAX_SWEEPS_FULL = 30;
+// From this many row blocks on, rounds 2.. of every sweep rotate only the
+// row pairs across the two blocks of a pair (half the inner steps): every
+// block still gets a full inner sweep in round 0 or 1, so every pair of rows
+// is visited at least once per sweep.  With fewer blocks this costs more extra
+// sweeps than it saves.
+constexpr int JAC_CROSS_MIN_NB = 16;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -600,6 +606,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             j.nb = h.nb;
             // odd block count (last block all padding) with at least 3 real blocks
             j.skip0 = (h.nb >= 4 && (h.nb - 1) * JAC_B >= h.R) ? 1 : 0;
+            j.cross_rounds = h.nb >= JAC_CROSS_MIN_NB ? 1 : 0;
             j.tol = (double)h.C * std::ldexp(1.0, -53);
             cj[b] = h.nb / 2 - j.skip0;
         }
