@@ -94,28 +94,87 @@ __device__ __forceinline__ double rsqrt_f64(double x)
 }
 
 // One workgroup per problem: G (l x l, FP64, lower triangle used) = L L^T,
-// right-looking by 16-column panels, the trailing matrix updated in place in
-// G.  Per panel: (1) one wave factors the 16 x 16 diagonal block in registers
-// (lane r holds row r; the column entries travel by readlane, so the 16
-// sequential column steps need no barrier or LDS round trip) and inverts it
-// by column-oriented substitution; (2) the panel below, L_iJ = G_iJ L_JJ^-T,
-// is formed by FP64 MFMA tiles into d.L and into LDS; (3) the trailing
-// update G_IK -= L_IJ L_KJ^T (lower tiles only) takes its MFMA operands from
-// the LDS copy of the panel, each wave loading the G tiles of a group of
-// tiles before multiplying them, so that memory latency is paid once per
-// group.  Three barriers per panel.  A pivot that falls below CHOL_PIVOT_REL
-// times the original diagonal entry sets the breakdown flag.  Writes L
-// column-major into d.L and the diagonal-block inverses into d.D.
+// right-looking by 16-column panels with a lookahead of one panel.  Wave 0
+// factors the 16 x 16 diagonal blocks in registers (lane r holds row r; the
+// column entries travel by readlane, so the 16 sequential column steps need
+// no barrier or LDS round trip) and inverts them by forward substitution on
+// all 16 right-hand sides at once.  Per panel J: (1) the panel below the
+// diagonal block, L_iJ = G_iJ L_JJ^-T, is formed by FP64 MFMA tiles into d.L
+// and into an LDS copy; (2) wave 0 applies the update of this panel to the
+// next diagonal block first and factors it, while the other waves update the
+// remaining lower tiles G_IK -= L_IJ L_KJ^T of the trailing matrix (operands
+// from the LDS copy of the panel; each wave loads the G tiles of a group
+// before multiplying them, so that memory latency is paid once per group).
+// Two barriers per panel.  A pivot that falls below CHOL_PIVOT_REL times the
+// original diagonal entry sets the breakdown flag.  Writes L column-major
+// into d.L and the diagonal-block inverses into d.D.
 constexpr int CHOL_GRP = 4;  // trailing tiles per wave and load group
+
+// Wave 0: factor the diagonal block held in Dt (w x w, identity padded),
+// invert it, publish L_JJ (Lb), L_JJ^-1 (Li) and the breakdown flag, write
+// the inverse to Dg.
+__device__ __forceinline__ void chol_factor_diag(double (*Dt)[17], double (*Lb)[17], double (*Li)[17],
+                                                 const double* g0, int J, int w, int* bad_s,
+                                                 GLB double* __restrict__ Dg)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, lq = lane >> 4;
+    double a[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) a[c] = (r < w && c < w && c <= r) ? Dt[r][c] : (r == c ? 1.0 : 0.0);
+    bool bad = false;
+    double dinv = 1.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const double pc = readlane_f64(a[c], c);
+        const double gref = (c < w) ? g0[J + c] : 1.0;
+        bad = bad || !(pc > CHOL_PIVOT_REL * gref) || !(pc < INFINITY);
+        const double inv = rsqrt_f64(pc);
+        const double lrc = (r == c) ? pc * inv : a[c] * inv;
+        a[c] = lrc;
+        if (r == c) dinv = inv;
+#pragma unroll
+        for (int k = c + 1; k < 16; ++k) {
+            const double lkc = readlane_f64(lrc, k);
+            if (r >= k) a[k] = fma(-lrc, lkc, a[k]);
+        }
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) Lb[r][c] = (c <= r) ? a[c] : 0.0;
+    }
+    if (lane == 0) *bad_s = bad ? 1 : 0;
+    // lane (r, q) holds row r of columns 4 q .. 4 q + 3 of the inverse; step t
+    // takes x_t = s_t / L_tt from lane (t, q) and updates the rows below it
+    double sv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) sv[j] = (r == 4 * lq + j) ? 1.0 : 0.0;
+#pragma unroll
+    for (int t2 = 0; t2 < 16; ++t2) {
+        const double it = readlane_f64(dinv, t2);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double xt = __shfl(sv[j], t2 + 16 * lq, 64) * it;
+            if (r > t2) sv[j] = fma(-a[t2], xt, sv[j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int c = 4 * lq + j;
+        const double x = (c <= r) ? sv[j] * dinv : 0.0;
+        Li[r][c] = x;
+        Dg[(int64_t)(J / 16) * 256 + r * 16 + c] = (r < w && c < w) ? x : 0.0;
+    }
+}
 
 template <int NT>
 __global__ __launch_bounds__(NT) void chol_rl_kernel(const QrDesc* __restrict__ descs)
 {
     constexpr int NW = NT / 64;
+    static_assert(NW >= 2, "wave 0 factors while the others update");
     extern __shared__ double dyn[];  // g0 (l), then the panel copy Lp (16 ceil((l - J - 16) / 16) < l rows x 17)
     __shared__ double Lb[16][17];
     __shared__ double Li[16][17];
-    __shared__ double idg[16];
+    __shared__ double Dt[16][17];
     __shared__ int bad_s;
     const QrDesc& d = descs[blockIdx.x];
     if (d.Qout == nullptr || *to_glb(d.flag)) return;
@@ -128,62 +187,16 @@ __global__ __launch_bounds__(NT) void chol_rl_kernel(const QrDesc* __restrict__ 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
     for (int i = tid; i < l; i += NT) g0[i] = G[(int64_t)i * l + i];
-    if (tid == 0) bad_s = 0;
+    if (tid < 256) {
+        const int r = tid >> 4, c = tid & 15;
+        Dt[r][c] = ld_or0(G, (int64_t)r * l + c, r < l && c < l);
+    }
+    __syncthreads();
+    if (wave == 0) chol_factor_diag(Dt, Lb, Li, g0, 0, min(16, l), &bad_s, Dg);
     __syncthreads();
 
     for (int J = 0; J < l; J += 16) {
         const int w = min(16, l - J);
-        // (1) diagonal block: factor and invert in wave 0
-        if (wave == 0) {
-            const int r = l16;
-            double a[16];
-#pragma unroll
-            for (int c = 0; c < 16; ++c)
-                a[c] = (r < w && c < w && c <= r) ? ld_or0(G, (int64_t)(J + r) * l + J + c, r < w && c < w)
-                                                  : (r == c ? 1.0 : 0.0);
-            bool bad = false;
-            double dinv = 1.0;
-#pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                const double pc = readlane_f64(a[c], c);
-                const double gref = (c < w) ? g0[J + c] : 1.0;
-                bad = bad || !(pc > CHOL_PIVOT_REL * gref) || !(pc < INFINITY);
-                const double inv = rsqrt_f64(pc);
-                const double lrc = (r == c) ? pc * inv : a[c] * inv;
-                a[c] = lrc;
-                if (r == c) dinv = inv;
-#pragma unroll
-                for (int k = c + 1; k < 16; ++k) {
-                    const double lkc = readlane_f64(lrc, k);
-                    if (r >= k) a[k] = fma(-lrc, lkc, a[k]);
-                }
-            }
-            if (lane < 16) {
-#pragma unroll
-                for (int c = 0; c < 16; ++c) Lb[r][c] = (c <= r) ? a[c] : 0.0;
-                idg[r] = dinv;
-            }
-            if (lane == 0) bad_s = bad ? 1 : 0;
-            // inverse, column c = lane: x_t = s_t / L_tt, then s_r -= L_rt x_t (r > t)
-            if (lane < 16) {
-                const int c = lane;
-                double sv[16], col[16];
-#pragma unroll
-                for (int rr = 0; rr < 16; ++rr) sv[rr] = (rr == c) ? 1.0 : 0.0;
-#pragma unroll
-                for (int t2 = 0; t2 < 16; ++t2) {
-                    col[t2] = (t2 < c) ? 0.0 : sv[t2] * idg[t2];
-#pragma unroll
-                    for (int rr = t2 + 1; rr < 16; ++rr) sv[rr] = fma(-Lb[rr][t2], col[t2], sv[rr]);
-                }
-#pragma unroll
-                for (int rr = 0; rr < 16; ++rr) {
-                    Li[rr][c] = col[rr];
-                    Dg[(int64_t)(J / 16) * 256 + rr * 16 + c] = (rr < w && c < w) ? col[rr] : 0.0;
-                }
-            }
-        }
-        __syncthreads();
         if (bad_s) {
             if (tid == 0) *to_glb(d.flag) = 1;
             return;
@@ -192,7 +205,7 @@ __global__ __launch_bounds__(NT) void chol_rl_kernel(const QrDesc* __restrict__ 
             const int r = e >> 4, c = e & 15;
             if (r < w && c < w) Rt[(int64_t)(J + c) * l + J + r] = (c <= r) ? Lb[r][c] : 0.0;
         }
-        // (2) panel below the diagonal block: L_iJ = G_iJ L_JJ^-T (row i - J - 16 of Lp)
+        // (1) panel below the diagonal block: L_iJ = G_iJ L_JJ^-T (row i - J - 16 of Lp)
         const int nrt = (l - J - 16 + 15) / 16;
         for (int t = wave; t < nrt; t += NW) {
             const int I0 = J + 16 + 16 * t;
@@ -215,44 +228,66 @@ __global__ __launch_bounds__(NT) void chol_rl_kernel(const QrDesc* __restrict__ 
             }
         }
         __syncthreads();
-        // (3) trailing update of the lower tiles: G_IK -= L_IJ L_KJ^T
+        if (nrt == 0) break;
         const int ntile = nrt * (nrt + 1) / 2;
-        for (int t0 = wave * CHOL_GRP; t0 < ntile; t0 += NW * CHOL_GRP) {
-            int ti[CHOL_GRP], tk[CHOL_GRP];
-            dbl4 acc[CHOL_GRP];
+        if (wave == 0) {
+            // (2a) lookahead: the next diagonal block (tile 0) first, then its factorisation
+            const int I0 = J + 16;
+            dbl4 acc;
 #pragma unroll
-            for (int g = 0; g < CHOL_GRP; ++g) {
-                const int t = t0 + g;
-                int a = 0, rem = (t < ntile) ? t : 0;
-                while (rem > a) {
-                    rem -= a + 1;
-                    ++a;
-                }
-                ti[g] = (t < ntile) ? a : -1;
-                tk[g] = rem;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = J + 16 + 16 * a + lq + 4 * r, j = J + 16 + 16 * rem + l16;
-                    acc[g][r] = ld_or0(G, (int64_t)i * l + j, t < ntile && i < l && j < l);
-                }
+            for (int r = 0; r < 4; ++r) {
+                const int i = I0 + lq + 4 * r, j = I0 + l16;
+                acc[r] = ld_or0(G, (int64_t)i * l + j, i < l && j < l);
             }
 #pragma unroll
-            for (int g = 0; g < CHOL_GRP; ++g) {
-                if (ti[g] < 0) continue;
-#pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) {
-                    const int k = 4 * s4 + lq;
-                    acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(-Lp[16 * ti[g] + l16][k], Lp[16 * tk[g] + l16][k],
-                                                                  acc[g], 0, 0, 0);
-                }
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int k = 4 * s4 + lq;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-Lp[l16][k], Lp[l16][k], acc, 0, 0, 0);
             }
 #pragma unroll
-            for (int g = 0; g < CHOL_GRP; ++g) {
-                if (ti[g] < 0) continue;
+            for (int r = 0; r < 4; ++r) Dt[lq + 4 * r][l16] = acc[r];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            chol_factor_diag(Dt, Lb, Li, g0, I0, min(16, l - I0), &bad_s, Dg);
+        } else {
+            // (2b) the other lower tiles of the trailing matrix: G_IK -= L_IJ L_KJ^T
+            for (int t0 = 1 + (wave - 1) * CHOL_GRP; t0 < ntile; t0 += (NW - 1) * CHOL_GRP) {
+                int ti[CHOL_GRP], tk[CHOL_GRP];
+                dbl4 acc[CHOL_GRP];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = J + 16 + 16 * ti[g] + lq + 4 * r, j = J + 16 + 16 * tk[g] + l16;
-                    if (i < l && j < l) G[(int64_t)i * l + j] = acc[g][r];
+                for (int g = 0; g < CHOL_GRP; ++g) {
+                    const int t = t0 + g;
+                    int a = 0, rem = (t < ntile) ? t : 0;
+                    while (rem > a) {
+                        rem -= a + 1;
+                        ++a;
+                    }
+                    ti[g] = (t < ntile) ? a : -1;
+                    tk[g] = rem;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = J + 16 + 16 * a + lq + 4 * r, j = J + 16 + 16 * rem + l16;
+                        acc[g][r] = ld_or0(G, (int64_t)i * l + j, t < ntile && i < l && j < l);
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < CHOL_GRP; ++g) {
+                    if (ti[g] < 0) continue;
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) {
+                        const int k = 4 * s4 + lq;
+                        acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(-Lp[16 * ti[g] + l16][k],
+                                                                      Lp[16 * tk[g] + l16][k], acc[g], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < CHOL_GRP; ++g) {
+                    if (ti[g] < 0) continue;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = J + 16 + 16 * ti[g] + lq + 4 * r, j = J + 16 + 16 * tk[g] + l16;
+                        if (i < l && j < l) G[(int64_t)i * l + j] = acc[g][r];
+                    }
                 }
             }
         }
