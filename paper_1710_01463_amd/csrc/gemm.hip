@@ -70,8 +70,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
     const GemmDesc& d = descs[b];
     if (d.skip && *to_glb(d.skip)) return;
     const int local = wi_.y;
-    const int m0 = (local / d.tiles_n) * BM;
-    const int n0 = (local % d.tiles_n) * BN;
+    int tm = local / d.tiles_n, tn = local % d.tiles_n;
+    if (d.lower) {
+        // local = tm (tm + 1) / 2 + tn, tn <= tm
+        tm = (int)((__builtin_sqrtf(8.0f * (float)local + 1.0f) - 1.0f) * 0.5f);
+        while (tm > 0 && tm * (tm + 1) / 2 > local) --tm;
+        while ((tm + 1) * (tm + 2) / 2 <= local) ++tm;
+        tn = local - tm * (tm + 1) / 2;
+    }
+    const int m0 = tm * BM;
+    const int n0 = tn * BN;
     const int M = d.M, N = d.N, K = d.K;
     const int64_t lda = d.lda, ldx = d.ldx;
     const int transA = d.transA, transX = d.transX;

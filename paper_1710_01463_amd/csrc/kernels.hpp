@@ -21,7 +21,7 @@ struct GemmDesc {
     int transA, transX, transC;
     int accumulate;
     int tiles_n;
-    int pad_;
+    int lower;         // 1: only the tiles on or below the diagonal of C (M == N, square tiles)
 };
 
 // Storage kinds of the operands of a GEMM launch and the MFMA used.

@@ -364,8 +364,10 @@ GemmLaunch add_gemm(Blob& B, GemmKind kind, Elem ea, Elem ex, Elem ec, std::vect
     for (size_t b = 0; b < descs.size(); ++b) {
         GemmDesc& d = descs[b];
         int t = 0;
+        if (d.lower && (tile != GT_64x64 || d.M != d.N)) d.lower = 0;  // lower-only needs square tiles
         if (d.M > 0 && d.N > 0 && d.K >= 0 && d.A != nullptr) t = tiles_of(d.M, d.N, tile);
         d.tiles_n = (d.N + gemm_tile_n(tile) - 1) / gemm_tile_n(tile);
+        if (d.lower && t > 0) t = d.tiles_n * (d.tiles_n + 1) / 2;
         counts[b] = t;
         total += t;
     }
@@ -381,7 +383,7 @@ GemmLaunch add_gemm(Blob& B, GemmKind kind, Elem ea, Elem ex, Elem ec, std::vect
     g.total = total;
     g.flops = 0.0;
     for (const GemmDesc& d : descs)
-        if (d.A != nullptr) g.flops += 2.0 * d.M * d.N * d.K;
+        if (d.A != nullptr) g.flops += d.lower ? (double)d.M * (d.M + 1) * d.K : 2.0 * d.M * d.N * d.K;
     return g;
 }
 
@@ -509,7 +511,9 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
                                 (int)h.n);
                 }
                 // pass 1: G = M^T M, L L^T = G, Q = M L^-T
+                // only the lower triangle of a Gram matrix is read (by the Cholesky)
                 dg1[b] = gd(M, l, 1, M, l, 0, G, l, l, l, (int)rows, flag);
+                dg1[b].lower = 1;
                 QrDesc& q = dq[b];
                 q.Min = M;
                 q.Qout = Qs;
@@ -523,6 +527,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
                 // pass 2 (final basis only), in place: G = Q^T Q, Q = Q L2^-T
                 if (final_stage) {
                     dg2[b] = gd(Qs, l, 1, Qs, l, 0, G, l, l, l, (int)rows, flag);
+                    dg2[b].lower = 1;
                     dq2[b] = q;
                     rowblk2[b] = rowblk[b];
                 }
