@@ -245,6 +245,23 @@ def main():
                           "launches_per_step": n_dom,
                           "flops_per_launch": fl_dom / n_dom if n_dom else None}
 
+    # sector post-selection over the batch's outputs (the 32 problems as one
+    # sector group, half of the 32 x 256 values kept); each timed call follows
+    # a fresh execute, since the call truncates the outputs in place
+    chi_ps = sum(pr.k for pr in probs) // 2
+    ps_ms = []
+    for _ in range(5):
+        plan.execute(As)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        chi_s = plan.postselect(chi_ps)
+        e1.record()
+        torch.cuda.synchronize()
+        ps_ms.append(e0.elapsed_time(e1))
+    assert int(chi_s.sum()) == chi_ps
+    result["postselect"] = {"sectors": len(probs), "candidates": int(sum(pr.k for pr in probs)), "chi": chi_ps,
+                            "us": float(np.median(ps_ms)) * 1e3}
+
     if not args.no_compare:
         # same-GPU full-SVD truncation on the same batch (FP64 Jacobi)
         log("[bench] full-SVD leg")

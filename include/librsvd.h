@@ -216,6 +216,28 @@ int rsvd_plan_profile_backward(rsvd_plan_t* plan, const void* const* dU, const v
                                const void* const* dVT, void* const* dA, double broadening, double* ms,
                                int64_t* launches, double* flops, int ncat, void* stream);
 
+/* rsvd_plan_postselect -- sector post-selection (paper Sec. III.A).  When a
+ * block-diagonal matrix (one block per symmetry sector) is truncated block by
+ * block, each sector's RSVD is run with a guessed rank chi'_s; afterwards the
+ * chi largest singular values over all sectors are kept, which sets the
+ * sector ranks chi_s.  The sectors are the problems of the plan, and the
+ * candidates are the k_kept values each kept in the plan's last
+ * rsvd_plan_execute (same output buffers, which must still be valid).
+ *   chi    >= 0, the total number of singular values to keep.
+ *   chi_s  device int64_t[batch], receives chi_s[b], the number kept in
+ *          problem b.  sum chi_s = min(chi, sum k_kept).
+ * The kept values are the first chi in the order (value descending, problem
+ * ascending, index ascending), so each problem keeps a prefix of its sorted S.
+ * For the dropped triplets of each problem the call adds their squared
+ * singular values to discarded_weight[b] (which stays the squared Frobenius
+ * error of that problem's truncation), zero-fills them in S, U (columns) and
+ * VT (rows), and sets k_kept[b] = chi_s[b].  A later rsvd_plan_backward
+ * treats the dropped triplets like any beyond k_kept.  At most 8192 problems.
+ * Asynchronous on stream, which must order it after the execute.  Returns
+ * RSVD_ERR_INVALID for a null plan or chi_s, chi < 0, more than 8192
+ * problems, or a plan that has not been executed. */
+int rsvd_plan_postselect(rsvd_plan_t* plan, int64_t chi, int64_t* chi_s, void* stream);
+
 /* Device bytes of the plan's workspace. */
 int64_t rsvd_plan_workspace_bytes(const rsvd_plan_t* plan);
 

@@ -167,3 +167,21 @@ def fullsvd_backward(A, k, dU, dS, dVT, delta=0.0, broad=0.0):
     if st != OK:
         raise RuntimeError(f"orc_fullsvd_backward status {st}")
     return dA
+
+
+def postselect(S_list, k_kept, chi):
+    """Sector post-selection (Sec. III.A): after one truncation per symmetry
+    sector, keep the chi largest singular values over all sectors.  S_list[b]
+    holds sector b's values (its first k_kept[b] are the candidates).  The
+    candidates are ranked by value descending, then sector ascending, then
+    index ascending, and the first chi are kept.  Returns the number kept per
+    sector.  Written as the definition: a full sort of all candidates."""
+    cand = []
+    for b, (S, kk) in enumerate(zip(S_list, k_kept)):
+        for j in range(int(kk)):
+            cand.append((-float(S[j]), b, j))
+    cand.sort()
+    chi_s = [0] * len(S_list)
+    for _, b, _ in cand[:max(0, int(chi))]:
+        chi_s[b] += 1
+    return chi_s

@@ -75,6 +75,8 @@ def lib():
                                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64),
                                                  ctypes.POINTER(ctypes.c_double), ctypes.c_int, _vp]
         L.rsvd_plan_profile_backward.restype = ctypes.c_int
+        L.rsvd_plan_postselect.argtypes = [_vp, _i64, _vp, _vp]
+        L.rsvd_plan_postselect.restype = ctypes.c_int
         L.rsvd_plan_workspace_bytes.argtypes = [_vp]
         L.rsvd_plan_workspace_bytes.restype = _i64
         L.rsvd_plan_destroy.argtypes = [_vp]

@@ -147,6 +147,17 @@ hipError_t launch_finish(const FinDesc* d, int nprob, const int* norm_map, int n
 // groups of 64 columns.
 hipError_t launch_signfix(const FinDesc* d, const int* map, int nprob, int total, int out_f64, hipStream_t s);
 
+// ---------------------------------------------------------------- sector post-selection
+// Keep the chi largest singular values over all problems of a plan (the
+// outputs its FinDesc table points to): chi_s[b] (device) receives how many
+// problem b keeps; the rest are dropped (weight added to w, zero-filled,
+// k_kept lowered).  At most SELECT_MAX_SECTORS problems.
+constexpr int SELECT_MAX_SECTORS = 8192;
+// max_candidates: sum over problems of k (bounds sum k_kept).
+hipError_t launch_postselect(const FinDesc* d, int nprob, int64_t max_candidates, int64_t chi, int64_t* chi_s,
+                             int out_f64, hipStream_t s);
+hipError_t init_select_kernels();
+
 // ---------------------------------------------------------------- staging
 // ||A||_F^2 (deterministic two-level FP64 reduction) and optional cast of A.
 struct StageDesc {

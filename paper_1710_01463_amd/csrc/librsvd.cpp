@@ -1104,7 +1104,10 @@ int plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsv
     {
         static std::once_flag once;
         static hipError_t init_err = hipSuccess;
-        std::call_once(once, [] { init_err = init_qr_kernels(); });
+        std::call_once(once, [] {
+            init_err = init_qr_kernels();
+            if (init_err == hipSuccess) init_err = init_select_kernels();
+        });
         if (init_err != hipSuccess) {
             plan_free(P);
             return fail(RSVD_ERR_HIP, std::string("kernel attributes: ") + hipGetErrorString(init_err));
@@ -1435,6 +1438,22 @@ int rsvd_plan_profile_backward(rsvd_plan_t* plan, const void* const* dU, const v
             flops[c] += prof.flops[i];
         }
     }
+    return RSVD_OK;
+}
+
+int rsvd_plan_postselect(rsvd_plan_t* plan, int64_t chi, int64_t* chi_s, void* stream)
+{
+    g_err.clear();
+    if (!plan) return fail(RSVD_ERR_INVALID, "plan is null");
+    if (!chi_s) return fail(RSVD_ERR_INVALID, "chi_s is null");
+    if (chi < 0) return fail(RSVD_ERR_INVALID, "chi must be >= 0");
+    if (!plan->blob_valid) return fail(RSVD_ERR_INVALID, "postselect needs a preceding rsvd_plan_execute");
+    if (plan->nprob > SELECT_MAX_SECTORS) return fail(RSVD_ERR_INVALID, "postselect supports at most 8192 problems");
+    const hipStream_t s = (hipStream_t)stream;
+    int64_t cand = 0;
+    for (const ProbHost& h : plan->probs) cand += h.k;
+    HIPCHK(launch_postselect(dp<FinDesc>(*plan, plan->finish.off_desc), plan->nprob, cand, chi, chi_s,
+                             plan->dt == RSVD_F64 ? 1 : 0, s));
     return RSVD_OK;
 }
 

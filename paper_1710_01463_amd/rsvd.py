@@ -166,6 +166,14 @@ class Plan:
                                           ms, nl, fl, nc, _stream()))
         return {name: (ms[i], int(nl[i]), fl[i]) for i, name in enumerate(L.PHASES)}
 
+    def postselect(self, chi):
+        """Sector post-selection (rsvd_plan_postselect): keep the chi largest
+        singular values over all problems of the last execute, in place.
+        Returns chi_s, a device int64 tensor with the number kept per problem."""
+        chi_s = torch.empty(len(self.problems), dtype=torch.int64, device=self.device)
+        L.check(L.lib().rsvd_plan_postselect(self._h, int(chi), chi_s.data_ptr(), _stream()))
+        return chi_s
+
     def _cotangent_ptrs(self, dU, dS, dVT, dA):
         n = len(self.problems)
         if not (len(dU) == len(dS) == len(dVT) == n):

@@ -20,7 +20,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ["rsvd_truncate", "fullsvd_truncate", "rsvd_plan_create", "rsvd_plan_execute",
               "rsvd_plan_destroy", "rsvd_last_error", "rsvd_plan_profile", "rsvd_gaussian",
-              "rsvd_plan_backward", "rsvd_plan_profile_backward"]:
+              "rsvd_plan_backward", "rsvd_plan_profile_backward", "rsvd_plan_postselect"]:
         assert n in names
 
 
@@ -71,6 +71,9 @@ def test_invalid_arguments_are_rejected_without_a_device():
     # backward without a plan
     arr = (vp * 1)(16)
     assert lib.rsvd_plan_backward(None, arr, arr, arr, arr, 0.0, None) == _lib.RSVD_ERR_INVALID
+    assert b"plan" in lib.rsvd_last_error()
+    # post-selection without a plan
+    assert lib.rsvd_plan_postselect(None, 4, dummy, None) == _lib.RSVD_ERR_INVALID
     assert b"plan" in lib.rsvd_last_error()
 
 

@@ -304,3 +304,66 @@ def test_rsvd_hmt_spectral_bound_power(q):
         r = oracle.rsvd(A, k, p, q, seed=900 + seed)
         errs.append(np.linalg.norm(A - r.Q @ (r.Q.T @ A), 2))
     assert np.mean(errs) <= bound
+
+
+# ---------------------------------------------------------------- sector post-selection
+def test_postselect_worked_example_with_ties():
+    """Hand-ranked example: the value 3 appears in sectors 0 and 1; sector 2 is empty."""
+    S = [np.array([5.0, 3.0, 1.0]), np.array([4.0, 3.0, 2.0]), np.array([7.0])]
+    kk = [3, 3, 0]
+    assert oracle.postselect(S, kk, 0) == [0, 0, 0]
+    assert oracle.postselect(S, kk, 1) == [1, 0, 0]
+    assert oracle.postselect(S, kk, 3) == [2, 1, 0]  # the tie at 3 goes to the lower sector
+    assert oracle.postselect(S, kk, 4) == [2, 2, 0]
+    assert oracle.postselect(S, kk, 5) == [2, 3, 0]
+    assert oracle.postselect(S, kk, 100) == [3, 3, 0]
+
+
+def test_postselect_block_diagonal_matches_svd_of_the_whole_matrix():
+    """For a block-diagonal A the singular values are the union of the blocks'
+    ones, so keeping the chi largest over the per-block full SVDs must keep
+    exactly the chi largest singular values of A (LAPACK on the whole matrix),
+    and the summed discarded weight must be the Eckart-Young error of the
+    rank-chi truncation of A."""
+    rng = np.random.default_rng(7)
+    sizes = [(30, 24), (18, 40), (50, 50), (12, 9)]
+    blocks = [rng.standard_normal((m, n)) * rng.uniform(0.2, 3.0) for m, n in sizes]
+    A = np.zeros((sum(m for m, _ in sizes), sum(n for _, n in sizes)))
+    r = c = 0
+    for B, (m, n) in zip(blocks, sizes):
+        A[r:r + m, c:c + n] = B
+        r += m
+        c += n
+    chi = 40
+    res = [oracle.fullsvd(B, min(B.shape)) for B in blocks]
+    chi_s = oracle.postselect([x.S for x in res], [x.k_kept for x in res], chi)
+    assert sum(chi_s) == chi
+    kept = np.sort(np.concatenate([x.S[:cs] for x, cs in zip(res, chi_s)]))[::-1]
+    ref = np.linalg.svd(A, compute_uv=False)
+    assert np.allclose(kept, ref[:chi], rtol=1e-12, atol=1e-12 * ref[0])
+    w = sum(x.w + np.sum(x.S[cs:x.k_kept] ** 2) for x, cs in zip(res, chi_s))
+    assert abs(w - np.sum(ref[chi:] ** 2)) <= 1e-10 * np.sum(A * A)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_postselect_invariants_random(seed):
+    """Count, dominance (every kept value >= every dropped one) and the prefix
+    property, on random sorted spectra with deliberate cross-sector ties."""
+    rng = np.random.default_rng(seed)
+    nsec = int(rng.integers(1, 9))
+    S, kk = [], []
+    pool = rng.uniform(0.0, 1.0, 6)
+    for _ in range(nsec):
+        k = int(rng.integers(0, 12))
+        v = np.sort(np.concatenate([rng.choice(pool, k // 2), rng.uniform(0, 1, k - k // 2)]))[::-1]
+        S.append(np.concatenate([v, np.zeros(3)]))
+        kk.append(int(rng.integers(0, k + 1)) if k else 0)
+    total = sum(kk)
+    for chi in range(0, total + 3):
+        cs = oracle.postselect(S, kk, chi)
+        assert sum(cs) == min(chi, total)
+        assert all(0 <= c <= k for c, k in zip(cs, kk))
+        kept = [S[b][j] for b in range(nsec) for j in range(cs[b])]
+        dropped = [S[b][j] for b in range(nsec) for j in range(cs[b], kk[b])]
+        if kept and dropped:
+            assert min(kept) >= max(dropped)
