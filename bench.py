@@ -262,6 +262,21 @@ def main():
     result["postselect"] = {"sectors": len(probs), "candidates": int(sum(pr.k for pr in probs)), "chi": chi_ps,
                             "us": float(np.median(ps_ms)) * 1e3}
 
+    # fixed-error truncation with an adaptive rank on one C2 matrix: rank 32,
+    # 64, 128, ... until the 1e-4 relative discarded-weight cut binds (the first
+    # call builds the plan of every rank tried; the second is timed)
+    if args.prec == "f64":
+        ad = dict(k0=32, k_max=512, delta=1e-4, p=16, q=2, seed=probs[0].seed)
+        P.rsvd_truncate_adaptive(As[0], ad["k0"], ad["k_max"], ad["delta"], ad["p"], ad["q"], seed=ad["seed"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, ad_w, ad_kk, ad_att = P.rsvd_truncate_adaptive(As[0], ad["k0"], ad["k_max"], ad["delta"], ad["p"],
+                                                                ad["q"], seed=ad["seed"])
+        torch.cuda.synchronize()
+        ad.update(matrix="C2 problem 0 (512x512)", attempts=ad_att, k_kept=int(ad_kk.item()),
+                  ms=(time.perf_counter() - t0) * 1e3)
+        result["adaptive"] = ad
+
     if not args.no_compare:
         # same-GPU full-SVD truncation on the same batch (FP64 Jacobi)
         log("[bench] full-SVD leg")

@@ -91,6 +91,29 @@ int rsvd_truncate(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t 
                   int64_t* k_kept, void* stream);
 
 /*
+ * rsvd_truncate_adaptive -- fixed-error truncation with an adaptive rank (the
+ * outlook of Sec. V: let the error target, not a rank guess, drive the
+ * RSVD).  Runs rsvd_truncate with k = k0, 2 k0, 4 k0, ... (capped at
+ * kcap = min(k_max, m, n)), the same seed throughout (so each sketch extends
+ * the previous one by new columns of Omega), until the discarded-weight cut
+ * binds inside the sketch (k_kept < k) or k reaches kcap.  Since
+ * w = ||A - U S V^T||_F^2 exactly for the computed factorisation, the result
+ * meets w <= delta_trunc ||A||_F^2 whenever k_kept < k; at the cap it is the
+ * rank-kcap truncation (exact when kcap = min(m, n)).
+ *   k0, k_max    1 <= k0 <= k_max
+ *   delta_trunc  finite, > 0 (required: it is the stopping rule)
+ *   U, S, VT     sized for kcap: U m x kcap (ldu >= kcap), S kcap, VT kcap x n;
+ *                triplets from k_kept on are zero
+ *   attempts     host int*, receives the number of RSVDs run (may be NULL)
+ * Other arguments as rsvd_truncate.  Each new k is a new cached plan shape.
+ * Blocking.  Returns RSVD_ERR_INVALID for bad sizes, delta_trunc <= 0 or
+ * null outputs, else the status of the last RSVD run. */
+int rsvd_truncate_adaptive(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t lda, int64_t k0,
+                           int64_t k_max, int64_t p, int64_t q, uint64_t seed, double delta_trunc,
+                           rsvd_prec_t prec, void* U, int64_t ldu, void* S, void* VT, int64_t ldvt,
+                           double* discarded_weight, int64_t* k_kept, int* attempts, void* stream);
+
+/*
  * fullsvd_truncate -- deterministic truncation by the full SVD (Alg. TSVD,
  * Sec. II.A), computed by block one-sided Jacobi in FP64 on A (m <= n) or A^T
  * (m > n).  Arguments as for rsvd_truncate.  Blocking, cached like it.

@@ -185,3 +185,20 @@ def postselect(S_list, k_kept, chi):
     for _, b, _ in cand[:max(0, int(chi))]:
         chi_s[b] += 1
     return chi_s
+
+
+def rsvd_adaptive(A, k0, k_max, p, q, seed, delta):
+    """Fixed-error RSVD with an adaptive rank (the outlook of Sec. V): the
+    RSVD of rank k = k0, 2 k0, 4 k0, ... (capped at min(k_max, m, n)) with one
+    seed, until the relative discarded-weight cut delta binds inside the
+    sketch (k_kept < k) or the cap is reached.  Returns (result, attempts)."""
+    A = _f64(A)
+    kcap = min(k_max, *A.shape)
+    k = min(k0, kcap)
+    attempts = 0
+    while True:
+        res = rsvd(A, k, p, q, seed, delta)
+        attempts += 1
+        if res.status != OK or res.k_kept < k or k >= kcap:
+            return res, attempts
+        k = min(2 * k, kcap)

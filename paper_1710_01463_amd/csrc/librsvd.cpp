@@ -1294,6 +1294,50 @@ int rsvd_truncate(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t 
                     k_kept, (hipStream_t)stream, false);
 }
 
+int rsvd_truncate_adaptive(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t lda, int64_t k0,
+                           int64_t k_max, int64_t p, int64_t q, uint64_t seed, double delta_trunc,
+                           rsvd_prec_t prec, void* U, int64_t ldu, void* S, void* VT, int64_t ldvt,
+                           double* discarded_weight, int64_t* k_kept, int* attempts, void* stream)
+{
+    g_err.clear();
+    if (dt != RSVD_F64 && dt != RSVD_F32) return fail(RSVD_ERR_INVALID, "unknown dtype");
+    if (prec != RSVD_PREC_F64 && prec != RSVD_PREC_F32 && prec != RSVD_PREC_BF16)
+        return fail(RSVD_ERR_INVALID, "unknown precision");
+    if (!(delta_trunc > 0.0) || !(delta_trunc < INFINITY))
+        return fail(RSVD_ERR_INVALID, "the adaptive rank needs a finite delta_trunc > 0");
+    if (k0 < 1 || k_max < k0) return fail(RSVD_ERR_INVALID, "need 1 <= k0 <= k_max");
+    if (m < 1 || n < 1) return fail(RSVD_ERR_INVALID, "m, n must be >= 1");
+    if (!U || !S || !VT || !discarded_weight || !k_kept) return fail(RSVD_ERR_INVALID, "null pointer argument");
+    const int64_t kcap = std::min(k_max, std::min(m, n));
+    if (ldu < kcap) return fail(RSVD_ERR_INVALID, "ldu < min(k_max, m, n)");
+    const hipStream_t s = (hipStream_t)stream;
+    int64_t k = std::min(k0, kcap);
+    int runs = 0;
+    for (;;) {
+        const int rc = one_shot(A, dt, m, n, lda, k, p, q, seed, delta_trunc, prec, U, ldu, S, VT, ldvt,
+                                discarded_weight, k_kept, s, false);
+        ++runs;
+        if (rc != RSVD_OK) {
+            if (attempts) *attempts = runs;
+            return rc;
+        }
+        int64_t kk = 0;
+        HIPCHK(hipMemcpy(&kk, k_kept, sizeof(int64_t), hipMemcpyDeviceToHost));
+        if (kk < k || k >= kcap) break;  // the cut binds inside the sketch, or the rank cap is reached
+        k = std::min(2 * k, kcap);
+    }
+    // triplets of the last run beyond its k_kept are zero; zero the ones beyond its k as well
+    const size_t es = dt == RSVD_F64 ? sizeof(double) : sizeof(float);
+    if (k < kcap) {
+        HIPCHK(hipMemset2DAsync((char*)U + k * es, ldu * es, 0, (kcap - k) * es, m, s));
+        HIPCHK(hipMemsetAsync((char*)S + k * es, 0, (kcap - k) * es, s));
+        HIPCHK(hipMemset2DAsync((char*)VT + k * ldvt * es, ldvt * es, 0, n * es, kcap - k, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    if (attempts) *attempts = runs;
+    return RSVD_OK;
+}
+
 int fullsvd_truncate(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t lda, int64_t k,
                      double delta_trunc, void* U, int64_t ldu, void* S, void* VT, int64_t ldvt,
                      double* discarded_weight, int64_t* k_kept, void* stream)

@@ -56,6 +56,23 @@ def rsvd_truncate(A, k, p=10, q=2, seed=0, delta=0.0, prec="f64"):
     return U, S, VT, w, kk
 
 
+def rsvd_truncate_adaptive(A, k0, k_max, delta, p=10, q=2, seed=0, prec="f64"):
+    """Fixed-error truncation (rsvd_truncate_adaptive): rank k0, 2 k0, ... up to
+    k_max until the delta cut binds.  Returns (U, S, VT, w, k_kept, attempts)
+    with outputs sized for min(k_max, m, n)."""
+    A = _check_matrix(A)
+    m, n = A.shape
+    U, S, VT = _outputs(m, n, k_max, A.dtype, A.device)
+    w = torch.empty(1, dtype=torch.float64, device=A.device)
+    kk = torch.empty(1, dtype=torch.int64, device=A.device)
+    att = ctypes.c_int(0)
+    L.check(L.lib().rsvd_truncate_adaptive(A.data_ptr(), _DT[A.dtype], m, n, A.stride(0), k0, k_max, p, q,
+                                           ctypes.c_uint64(seed), float(delta), L.PREC[prec], U.data_ptr(),
+                                           U.shape[1], S.data_ptr(), VT.data_ptr(), n, w.data_ptr(),
+                                           kk.data_ptr(), ctypes.byref(att), _stream()))
+    return U, S, VT, w, kk, att.value
+
+
 def fullsvd_truncate(A, k, delta=0.0):
     """Truncation by the full SVD (Alg. TSVD), block one-sided Jacobi in FP64."""
     A = _check_matrix(A)

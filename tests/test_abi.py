@@ -20,7 +20,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ["rsvd_truncate", "fullsvd_truncate", "rsvd_plan_create", "rsvd_plan_execute",
               "rsvd_plan_destroy", "rsvd_last_error", "rsvd_plan_profile", "rsvd_gaussian",
-              "rsvd_plan_backward", "rsvd_plan_profile_backward", "rsvd_plan_postselect"]:
+              "rsvd_plan_backward", "rsvd_plan_profile_backward", "rsvd_plan_postselect",
+              "rsvd_truncate_adaptive"]:
         assert n in names
 
 
@@ -72,6 +73,13 @@ def test_invalid_arguments_are_rejected_without_a_device():
     arr = (vp * 1)(16)
     assert lib.rsvd_plan_backward(None, arr, arr, arr, arr, 0.0, None) == _lib.RSVD_ERR_INVALID
     assert b"plan" in lib.rsvd_last_error()
+    # adaptive rank: delta must be > 0, k0 <= k_max
+    st = lib.rsvd_truncate_adaptive(dummy, 0, 10, 10, 10, 2, 8, 2, 1, ctypes.c_uint64(1), 0.0, 0, dummy, 8,
+                                    dummy, dummy, 10, dummy, dummy, None, None)
+    assert st == _lib.RSVD_ERR_INVALID and b"delta" in lib.rsvd_last_error()
+    st = lib.rsvd_truncate_adaptive(dummy, 0, 10, 10, 10, 9, 8, 2, 1, ctypes.c_uint64(1), 1e-3, 0, dummy, 8,
+                                    dummy, dummy, 10, dummy, dummy, None, None)
+    assert st == _lib.RSVD_ERR_INVALID
     # post-selection without a plan
     assert lib.rsvd_plan_postselect(None, 4, dummy, None) == _lib.RSVD_ERR_INVALID
     assert b"plan" in lib.rsvd_last_error()

@@ -367,3 +367,34 @@ def test_postselect_invariants_random(seed):
         dropped = [S[b][j] for b in range(nsec) for j in range(cs[b], kk[b])]
         if kept and dropped:
             assert min(kept) >= max(dropped)
+
+
+# ---------------------------------------------------------------- adaptive rank
+def test_adaptive_rank_exact_low_rank():
+    """A of exact rank r: the cut binds at k_kept = r as soon as the sketch
+    holds r directions, so the rank doubles from k0 until it first exceeds r,
+    and the result reproduces A."""
+    rng = np.random.default_rng(3)
+    m, n, r = 90, 70, 21
+    s = np.linspace(3.0, 1.0, r)
+    U, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    A = (U * s) @ V.T
+    for k0, expect in [(4, 4), (6, 3), (22, 1), (21, 2)]:  # 4 8 16 32 | 6 12 24 | 22 | 21 42
+        res, att = oracle.rsvd_adaptive(A, k0, 70, 5, 1, 11, 1e-12)
+        assert att == expect, (k0, att)
+        assert res.k_kept == r
+        assert np.allclose((res.U[:, :r] * res.S[:r]) @ res.VT[:r], A, atol=1e-12)
+
+
+def test_adaptive_rank_meets_the_target_or_stops_at_the_cap():
+    """Decaying spectrum: the final truncation meets w <= delta ||A||^2 when the
+    cut binds; with a cap below the needed rank it stops at the cap."""
+    A = wl.make_matrix(128, 100, np.exp(-0.08 * np.arange(1, 101)), 5)
+    a2 = np.sum(A * A)
+    res, att = oracle.rsvd_adaptive(A, 4, 100, 8, 2, 13, 1e-6)
+    assert res.k_kept < min(128, 100) and res.w <= 1e-6 * a2 * (1 + 1e-9)
+    assert att >= 2
+    # the exact truncation needs more than 8 triplets for 1e-6: capped at 8
+    res8, att8 = oracle.rsvd_adaptive(A, 4, 8, 8, 2, 13, 1e-6)
+    assert res8.k_kept == 8 and res8.w > 1e-6 * a2 and att8 == 2
