@@ -156,6 +156,40 @@ def diff_leg(args, P, torch, wl):
     }
 
 
+def tebd_leg(P, torch, wl):
+    """The TEBD compression shapes (Sec. III): 64 product updates (200 x 500,
+    ratio 1/2) and 32 block updates (500 x 500, ratio 1/5) at chi = 100, FP64,
+    each batch one graph launch, against the same-GPU full-SVD truncation."""
+    import numpy as np
+    out = {}
+    for name, W in (("product_200x500", wl.tebd_product(64)), ("block_500x500", wl.tebd_block(32))):
+        log(f"[bench] TEBD leg: {name}")
+        probs = W.problems
+        As = [torch.from_numpy(pr.matrix()).cuda() for pr in probs]
+        plan = P.Plan([dict(m=pr.m, n=pr.n, k=pr.k, p=pr.p, q=pr.q, seed=pr.seed) for pr in probs],
+                      torch.float64, "f64", graph=True)
+        fplan = P.Plan([dict(m=pr.m, n=pr.n, k=pr.k) for pr in probs], torch.float64, "f64", fullsvd=True)
+        res = {}
+        for key, pl, steps in (("rsvd", plan, 10), ("fullsvd", fplan, 3)):
+            pl.execute(As)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                pl.execute(As)
+            torch.cuda.synchronize()
+            res[key] = (time.perf_counter() - t0) / steps * 1e3
+            _, w, _, info = pl.execute(As)
+            torch.cuda.synchronize()
+            assert np.all(info.cpu().numpy() == 0)
+            res[key + "_w"] = w.cpu().numpy()
+        out[name] = {"batch": len(probs), "rsvd_per_s": len(probs) / (res["rsvd"] / 1e3), "rsvd_ms": res["rsvd"],
+                     "fullsvd_per_s": len(probs) / (res["fullsvd"] / 1e3), "speedup_vs_fullsvd": res["fullsvd"] / res["rsvd"],
+                     "eps_F_over_delta_EY_rsvd": float(np.mean(np.sqrt(res["rsvd_w"] / res["fullsvd_w"])))}
+        plan.close()
+        fplan.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -314,6 +348,9 @@ def main():
             "eps_F_over_delta_EY_rsvd": eps_ratio,
             "eps_F_over_delta_EY_fullsvd": 1.0,
         }
+
+    if not args.no_compare and args.prec == "f64":
+        result["tebd"] = tebd_leg(P, torch, wl)
 
     if not args.no_diff:
         result["differentiation"] = diff_leg(args, P, torch, wl)

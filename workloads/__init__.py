@@ -170,6 +170,26 @@ def c5(batch: int = 64) -> Workload:
                     "k=128 p=16 q=2", probs, "f32", ("f32",))
 
 
+def tebd_product(batch: int = 64, chi: int = 100, K: int = 2, d: int = 5) -> Workload:
+    """TEBD product update (Sec. III): a (chi K) x (chi d) matrix compressed to
+    rank chi (ratio 1/min(K, d)); power-law spectrum s_i = i^-2."""
+    m, n = chi * K, chi * d
+    s = spectrum_power(min(m, n), 2.0)
+    probs = [Problem(m, n, chi, 10, 2, 2000 * 6 + b, 1000 * 6 + b, s) for b in range(batch)]
+    return Workload("TEBD-P", f"{batch} x {m}x{n} (chi={chi}, K={K}, d={d}), s_i = i^-2, k={chi} p=10 q=2",
+                    probs, "f64", ("f64",))
+
+
+def tebd_block(batch: int = 32, chi: int = 100, d: int = 5) -> Workload:
+    """TEBD block update (Sec. III): a (chi d) x (chi d) matrix compressed to
+    rank chi (ratio 1/d); power-law spectrum s_i = i^-2."""
+    m = chi * d
+    s = spectrum_power(m, 2.0)
+    probs = [Problem(m, m, chi, 10, 2, 2000 * 7 + b, 1000 * 7 + b, s) for b in range(batch)]
+    return Workload("TEBD-B", f"{batch} x {m}x{m} (chi={chi}, d={d}), s_i = i^-2, k={chi} p=10 q=2",
+                    probs, "f64", ("f64",))
+
+
 def cotangents(m: int, n: int, k: int, seed: int):
     """Seeded Gaussian cotangents (dU m x k, dS k, dVT k x n) for the adjoint."""
     rng = np.random.default_rng(seed)
