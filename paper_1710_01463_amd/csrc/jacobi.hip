@@ -735,8 +735,15 @@ __global__ __launch_bounds__(64 * SF_WAVES) void signfix_kernel(const FinDesc* _
             }
         }
     }
-    // rows of VT: wave w takes rows j0 + w, j0 + w + SF_WAVES, ...
+    // rows of VT: wave w takes rows j0 + w, j0 + w + SF_WAVES, ...; rows past
+    // k_kept are zeroed (they are zero already unless V^T came from a product
+    // with non-finite factors)
     for (int r = wave; r < 64; r += SF_WAVES) {
+        if (j0 + r >= kk && j0 + r < k) {
+            GLB TO* __restrict__ zrow = VT + (int64_t)(j0 + r) * d.ldvt;
+            for (int x = lane; x < n; x += 64) zrow[x] = (TO)0;
+            continue;
+        }
         if (!flip_s[r] || j0 + r >= k) continue;
         GLB TO* __restrict__ vrow = VT + (int64_t)(j0 + r) * d.ldvt;
         for (int x0 = lane; x0 < n; x0 += 64 * 8) {
