@@ -31,6 +31,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the full-SVD and one-at-a-time legs")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the post-selection and adaptive-rank legs (only the C2 plan runs)")
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-diff", action="store_true", help="skip the forward + adjoint leg")
     ap.add_argument("--diff-batch", type=int, default=64)
@@ -298,7 +300,7 @@ def main():
     # a fresh execute, since the call truncates the outputs in place
     chi_ps = sum(pr.k for pr in probs) // 2
     ps_ms = []
-    for _ in range(5):
+    for _ in range(0 if args.no_extra else 5):
         plan.execute(As)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -306,14 +308,15 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ps_ms.append(e0.elapsed_time(e1))
-    assert int(chi_s.sum()) == chi_ps
-    result["postselect"] = {"sectors": len(probs), "candidates": int(sum(pr.k for pr in probs)), "chi": chi_ps,
-                            "us": float(np.median(ps_ms)) * 1e3}
+    if ps_ms:
+        assert int(chi_s.sum()) == chi_ps
+        result["postselect"] = {"sectors": len(probs), "candidates": int(sum(pr.k for pr in probs)), "chi": chi_ps,
+                                "us": float(np.median(ps_ms)) * 1e3}
 
     # fixed-error truncation with an adaptive rank on one C2 matrix: rank 32,
     # 64, 128, ... until the 1e-4 relative discarded-weight cut binds (the first
     # call builds the plan of every rank tried; the second is timed)
-    if args.prec == "f64":
+    if args.prec == "f64" and not args.no_extra:
         ad = dict(k0=32, k_max=512, delta=1e-4, p=16, q=2, seed=probs[0].seed)
         P.rsvd_truncate_adaptive(As[0], ad["k0"], ad["k_max"], ad["delta"], ad["p"], ad["q"], seed=ad["seed"])
         torch.cuda.synchronize()
