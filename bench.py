@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the post-selection and adaptive-rank legs (only the C2 plan runs)")
     ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the shape heuristic's GEMM tiles instead of tuning them on the first execute")
     ap.add_argument("--no-diff", action="store_true", help="skip the forward + adjoint leg")
     ap.add_argument("--diff-batch", type=int, default=64)
     ap.add_argument("--diff-steps", type=int, default=5)
@@ -236,7 +238,13 @@ def main():
     dtype = torch.float64 if args.prec == "f64" else torch.float32
     As = [torch.from_numpy(A).to(dtype).cuda() for A in mats]
     plist = [dict(m=pr.m, n=pr.n, k=pr.k, p=pr.p, q=pr.q, seed=pr.seed) for pr in probs]
-    plan = P.Plan(plist, dtype, args.prec, graph=True)
+    plan = P.Plan(plist, dtype, args.prec, graph=True, tune=not args.no_tune)
+    heuristic_tiles = plan.tiles()
+    t0 = time.perf_counter()
+    plan.execute(As)  # with tuning: times every tile of each forward product, then executes
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    log(f"[bench] first execute {tune_s:.2f} s, tiles {plan.tiles()}")
 
     log(f"[bench] warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -275,6 +283,21 @@ def main():
                    "batch": len(probs), "m": 512, "n": 512, "k": 256, "p": 16, "q": 2},
         "gemm_tflops": gemm_flops / (ms / 1e3) / 1e12,
     }
+    if not args.no_tune:
+        # the same batch with the shape heuristic's tiles, timed the same way
+        hplan = P.Plan(plist, dtype, args.prec, graph=True)
+        for _ in range(max(args.warmup, 1)):
+            hplan.execute(As)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            hplan.execute(As)
+        torch.cuda.synchronize()
+        hms = (time.perf_counter() - t0) / args.steps * 1e3
+        hplan.close()
+        result["tiles"] = {"tuned": [f"{a}x{b}" for a, b in plan.tiles()],
+                           "heuristic": [f"{a}x{b}" for a, b in heuristic_tiles],
+                           "tuning_execute_s": round(tune_s, 3), "heuristic_ms_per_step": hms}
 
     # per-phase breakdown (eager launches, HIP events on the plan's stream) and
     # the roofline of the dominant kernel

@@ -156,6 +156,7 @@ typedef struct rsvd_plan rsvd_plan_t;
 #define RSVD_PLAN_GRAPH 2u   /* capture the launch sequence into a HIP graph on first execute */
 #define RSVD_PLAN_SAVE 4u    /* keep every intermediate basis and the adjoint workspace for rsvd_plan_backward */
 #define RSVD_PLAN_NO_REFINE 8u /* form B = Q^T A in the sketch precision instead of FP64 (accuracy study) */
+#define RSVD_PLAN_TUNE 16u     /* choose the workgroup tile of every forward product by measurement (below) */
 
 /* Validates the problems, sizes and allocates the plan's device workspace.
  * Returns RSVD_ERR_INVALID for bad problem descriptions. */
@@ -260,6 +261,41 @@ int rsvd_plan_profile_backward(rsvd_plan_t* plan, const void* const* dU, const v
  * RSVD_ERR_INVALID for a null plan or chi_s, chi < 0, more than 8192
  * problems, or a plan that has not been executed. */
 int rsvd_plan_postselect(rsvd_plan_t* plan, int64_t chi, int64_t* chi_s, void* stream);
+
+/* Tile autotuning (batching of uneven problem lists).  A plan created with
+ * RSVD_PLAN_TUNE spends its first rsvd_plan_execute (or rsvd_plan_profile)
+ * measuring, before the normal execute: every forward product that is not
+ * gathered, accumulating or lower-triangular (the sketch and power-iteration
+ * products A Omega, A^T Q, A Z, the projection B = Q^T A and the products of
+ * the triangular-factor small SVD) is launched with each workgroup tile
+ * (64x64, 128x64, 64x128, 128x128 outputs) on the call's own inputs, one
+ * warm-up and three timed launches each (HIP events), and the fastest is kept
+ * for the life of the plan and captured in its graph.  All tiles give
+ * bit-identical products (each output element is summed in the same K order).
+ * Choices are remembered per launch signature (kinds, element types and every
+ * problem's M, N, K and transposes) in a process-wide table, so a later plan
+ * with the same shapes measures nothing; when the environment variable
+ * RSVD_TUNE_CACHE names a file, the table is read from it once and rewritten
+ * (a JSON object, signature -> "BMxBN") after each new entry.  The tuning
+ * execute synchronizes the stream and is blocking.  Without RSVD_PLAN_TUNE a
+ * shape heuristic picks the tile (128x64 for products with M >= 512 and
+ * N <= 160 that give at least 512 such tiles, else 64x64).
+ *
+ * rsvd_plan_tiles -- the tile in use for each of those products, in launch
+ * order: tiles[2 i] = rows, tiles[2 i + 1] = columns of product i's output
+ * tile, for i < min(cap, *count); *count = number of such products.  Host
+ * pointers.  Returns RSVD_ERR_INVALID for a null plan or count, cap < 0, or
+ * tiles null with cap > 0. */
+int rsvd_plan_tiles(const rsvd_plan_t* plan, int32_t* tiles, int64_t cap, int64_t* count);
+
+/* rsvd_plan_set_tiles -- fixes the tile of each of those products (same
+ * order and encoding as rsvd_plan_tiles; count must equal its *count), for
+ * example to replay tiles tuned offline.  The plan counts as tuned afterwards
+ * (RSVD_PLAN_TUNE then measures nothing) and its graph is re-captured at the
+ * next execute.  Waits for the device to be idle; no execute of the plan may
+ * be in flight on another thread.  Returns RSVD_ERR_INVALID for a null plan,
+ * a wrong count or a tile that is not one of the four. */
+int rsvd_plan_set_tiles(rsvd_plan_t* plan, const int32_t* tiles, int64_t count);
 
 /* Device bytes of the plan's workspace. */
 int64_t rsvd_plan_workspace_bytes(const rsvd_plan_t* plan);

@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(_HERE, "librsvd.so")
 RSVD_OK, RSVD_ERR_INVALID, RSVD_ERR_ALLOC, RSVD_ERR_HIP, RSVD_ERR_NONFINITE, RSVD_ERR_NOCONV = 0, -1, -2, -3, -4, -5
 RSVD_F64, RSVD_F32 = 0, 1
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
-PLAN_FULLSVD, PLAN_GRAPH, PLAN_SAVE, PLAN_NO_REFINE = 1, 2, 4, 8
+PLAN_FULLSVD, PLAN_GRAPH, PLAN_SAVE, PLAN_NO_REFINE, PLAN_TUNE = 1, 2, 4, 8, 16
 
 PHASES = ["stage", "omega", "sketch", "gram", "chol", "trsm", "householder", "project", "jacobi",
           "finish", "backproj", "signfix", "other", "bw_gemm", "bw_small"]
@@ -81,6 +81,10 @@ def lib():
         L.rsvd_plan_profile_backward.restype = ctypes.c_int
         L.rsvd_plan_postselect.argtypes = [_vp, _i64, _vp, _vp]
         L.rsvd_plan_postselect.restype = ctypes.c_int
+        L.rsvd_plan_tiles.argtypes = [_vp, _vp, _i64, _vp]
+        L.rsvd_plan_tiles.restype = ctypes.c_int
+        L.rsvd_plan_set_tiles.argtypes = [_vp, _vp, _i64]
+        L.rsvd_plan_set_tiles.restype = ctypes.c_int
         L.rsvd_plan_workspace_bytes.argtypes = [_vp]
         L.rsvd_plan_workspace_bytes.restype = _i64
         L.rsvd_plan_destroy.argtypes = [_vp]

@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -108,6 +110,9 @@ struct GemmLaunch {
     size_t off_desc, off_begin;
     int total;
     double flops;  // algorithmic 2 M N K summed over the problems
+    int slot = -1;     // index among the plan's tunable forward launches, -1 if not tunable
+    int cap = 0;       // workgroups reserved in the item map (the 64 x 64 count, the largest)
+    uint64_t sig = 0;  // shape signature: kinds, element types and every problem's M, N, K, transposes
 };
 
 // Events around every launch of an eager execute (rsvd_plan_profile).
@@ -198,6 +203,11 @@ struct rsvd_plan {
     Profiler* prof = nullptr;  // set only during rsvd_plan_profile
     uint64_t fwd_gen = 0;      // bumped whenever the forward descriptors are rebuilt
     bool fwd_saved = false;    // a forward execute of a RSVD_PLAN_SAVE plan was enqueued
+    // tile autotuning (RSVD_PLAN_TUNE): per tunable forward launch, the tile in use
+    // and the tuned override (-1: the shape heuristic)
+    std::vector<int> slot_tile, tile_ovr;
+    bool tuner = false;  // the eager execute under way times the candidate tiles
+    bool tuned = false;
     struct BwStage {
         GemmLaunch c, qs, r, da, qprev;
         IdxLaunch sym, tri, trsm;
@@ -373,13 +383,12 @@ std::vector<int> item_map(const std::vector<int>& counts)
     return map;
 }
 
-GemmLaunch add_gemm(Blob& B, GemmKind kind, Elem ea, Elem ex, Elem ec, std::vector<GemmDesc>& descs)
+// Tile-dependent fields of a launch's descriptors (tiles_n, lower) and each
+// problem's workgroup count.
+std::vector<int> finalize_descs(std::vector<GemmDesc>& descs, GemmTile tile, int* total)
 {
-    bool gather = false;
-    for (const GemmDesc& d : descs) gather = gather || (d.A != nullptr && d.gather != nullptr);
-    const GemmTile tile = gather ? GT_64x64 : choose_tile(descs);
     std::vector<int> counts(descs.size(), 0);
-    int total = 0;
+    *total = 0;
     for (size_t b = 0; b < descs.size(); ++b) {
         GemmDesc& d = descs[b];
         int t = 0;
@@ -388,9 +397,55 @@ GemmLaunch add_gemm(Blob& B, GemmKind kind, Elem ea, Elem ex, Elem ec, std::vect
         d.tiles_n = (d.N + gemm_tile_n(tile) - 1) / gemm_tile_n(tile);
         if (d.lower && t > 0) t = d.tiles_n * (d.tiles_n + 1) / 2;
         counts[b] = t;
-        total += t;
+        *total += t;
     }
+    return counts;
+}
+
+// FNV-1a over the fields that decide a launch's cost: kinds, element types
+// and every problem's shape and transposes (not its pointers).
+uint64_t gemm_signature(GemmKind kind, Elem ea, Elem ex, Elem ec, const std::vector<GemmDesc>& descs)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](int64_t v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (uint64_t)((v >> (8 * i)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    mix(kind), mix(ea), mix(ex), mix(ec), mix((int64_t)descs.size());
+    for (const GemmDesc& d : descs) {
+        const bool live = d.A != nullptr && d.M > 0 && d.N > 0;
+        mix(live ? d.M : 0), mix(live ? d.N : 0), mix(live ? d.K : 0);
+        mix(live ? d.transA * 4 + d.transX * 2 + d.transC : 0);
+    }
+    return h;
+}
+
+// forced >= 0 fixes the tile of a tunable launch (slot >= 0: no gathered,
+// accumulating or lower-only product); the item map of a tunable launch is
+// sized for the 64 x 64 tiling so that any tile fits the same blob layout.
+GemmLaunch add_gemm(Blob& B, GemmKind kind, Elem ea, Elem ex, Elem ec, std::vector<GemmDesc>& descs,
+                    int slot = -1, int forced = -1)
+{
+    bool gather = false, special = false;
+    for (const GemmDesc& d : descs) {
+        gather = gather || (d.A != nullptr && d.gather != nullptr);
+        special = special || (d.A != nullptr && (d.lower || d.accumulate));
+    }
+    const bool tunable = slot >= 0 && !gather && !special;
+    GemmTile tile = gather ? GT_64x64 : choose_tile(descs);
+    if (tunable && forced >= 0) tile = (GemmTile)forced;
     GemmLaunch g;
+    if (tunable) {
+        g.sig = gemm_signature(kind, ea, ex, ec, descs);
+        for (const GemmDesc& d : descs)
+            if (d.M > 0 && d.N > 0 && d.K >= 0 && d.A != nullptr) g.cap += tiles_of(d.M, d.N, GT_64x64);
+    }
+    int total = 0;
+    const std::vector<int> counts = finalize_descs(descs, tile, &total);
+    std::vector<int> map = item_map(counts);
+    if (tunable && map.size() < 2 * (size_t)g.cap) map.resize(2 * (size_t)g.cap, 0);
     g.kind = kind;
     g.tile = tile;
     g.gather = gather;
@@ -398,8 +453,9 @@ GemmLaunch add_gemm(Blob& B, GemmKind kind, Elem ea, Elem ex, Elem ec, std::vect
     g.ex = ex;
     g.ec = ec;
     g.off_desc = B.add(descs);
-    g.off_begin = B.add(item_map(counts));
+    g.off_begin = B.add(map);
     g.total = total;
+    g.slot = tunable ? slot : -1;
     g.flops = 0.0;
     for (const GemmDesc& d : descs)
         if (d.A != nullptr) g.flops += d.lower ? (double)d.M * (d.M + 1) * d.K : 2.0 * d.M * d.N * d.K;
@@ -447,6 +503,16 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
     const Elem es = P.e_store;
     const int out_f64 = (P.dt == RSVD_F64);
     (void)out_f64;
+    // forward products whose tile the autotuner may choose, numbered in build order
+    int nslot = 0;
+    P.slot_tile.clear();
+    auto tgemm = [&](GemmKind kind, Elem ea, Elem ex, Elem ec, std::vector<GemmDesc>& d) {
+        const int slot = nslot++;
+        const int forced = slot < (int)P.tile_ovr.size() ? P.tile_ovr[slot] : -1;
+        GemmLaunch g = add_gemm(B, kind, ea, ex, ec, d, slot, forced);
+        P.slot_tile.push_back(g.slot >= 0 ? (int)g.tile : -1);
+        return g;
+    };
 
     // staging: ||A||^2 and the optional cast
     {
@@ -552,7 +618,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
                 }
             }
             // X operand element of the sketch GEMMs: Omega at s = 0, FP64 bases afterwards
-            P.g_sketch.push_back(add_gemm(B, gk, ea_sk, s == 0 ? P.e_sketch : E_F64, P.e_y, dsk));
+            P.g_sketch.push_back(tgemm(gk, ea_sk, s == 0 ? P.e_sketch : E_F64, P.e_y, dsk));
             P.g_gram1.push_back(add_gemm(B, GK_F64, P.e_y, P.e_y, E_F64, dg1));
             P.g_gram2.push_back(add_gemm(B, GK_F64, E_F64, E_F64, E_F64, dg2));
             std::vector<int> ones(np, 1);
@@ -601,7 +667,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
                 dq2[b] = q;
                 rowblk2[b] = rowblk[b];
             }
-            P.g_lqbt = add_gemm(B, GK_F64, es, E_F64, E_F64, dbt);
+            P.g_lqbt = tgemm(GK_F64, es, E_F64, E_F64, dbt);
             P.g_lqgram1 = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, dg1);
             P.g_lqgram2 = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, dg2);
             P.lq_qr[0] = add_idx(B, dq, ones);
@@ -619,7 +685,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
                     dx[b] = gd(wsp<double>(P, h.o_bt), h.l, 1, wsp<double>(P, h.o_qb), h.l, 0, wsp<double>(P, h.o_b),
                                h.l, h.l, h.l, (int)h.n);
             }
-            P.g_lqx = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, dx);
+            P.g_lqx = tgemm(GK_F64, E_F64, E_F64, E_F64, dx);
         }
         // B = Q^T A in FP64 from the stored A (the other problems)
         {
@@ -642,9 +708,9 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
                     }
                 }
                 const GemmKind gk2 = P.prec == RSVD_PREC_F32 ? GK_F32 : GK_BF16;
-                P.g_b = add_gemm(B, gk2, E_F64, P.need_cast ? P.e_sketch : es, E_F64, d);
+                P.g_b = tgemm(gk2, E_F64, P.need_cast ? P.e_sketch : es, E_F64, d);
             } else {
-                P.g_b = add_gemm(B, GK_F64, E_F64, es, E_F64, d);
+                P.g_b = tgemm(GK_F64, E_F64, es, E_F64, d);
             }
         }
     } else {
@@ -783,7 +849,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             }
             // W holds the finishing step's output type (it is written like V^T)
             const Elem eo = P.dt == RSVD_F64 ? E_F64 : E_F32;
-            P.g_lqvt = add_gemm(B, GK_F64, eo, E_F64, eo, dv);
+            P.g_lqvt = tgemm(GK_F64, eo, E_F64, eo, dv);
         }
     }
     P.hb = std::move(B);
@@ -805,9 +871,156 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
 
 template <typename T> const T* dp(const rsvd_plan& P, size_t off) { return (const T*)(P.dblob + off); }
 
-int gemm(const rsvd_plan& P, const GemmLaunch& g, hipStream_t s, int cat)
+// ---------------------------------------------------------------- tile autotuner
+// Process-wide table: launch signature -> the fastest tile measured for it.
+// With RSVD_TUNE_CACHE naming a file, the table is read from it once and
+// written back (a flat JSON object, signature -> "BMxBN") after every new entry.
+std::mutex g_tune_mu;
+std::map<uint64_t, int> g_tune;
+bool g_tune_loaded = false;
+
+const char* tile_name(int t)
+{
+    switch (t) {
+    case GT_64x64: return "64x64";
+    case GT_128x64: return "128x64";
+    case GT_64x128: return "64x128";
+    case GT_128x128: return "128x128";
+    }
+    return "?";
+}
+
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = getenv("RSVD_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    fclose(f);
+    // pairs of quoted strings: "<16 hex digits>": "<tile>"
+    std::vector<std::string> q;
+    for (size_t i = 0; i < text.size(); ++i) {
+        if (text[i] != '"') continue;
+        const size_t j = text.find('"', i + 1);
+        if (j == std::string::npos) break;
+        q.push_back(text.substr(i + 1, j - i - 1));
+        i = j;
+    }
+    for (size_t i = 0; i + 1 < q.size(); i += 2) {
+        char* end = nullptr;
+        const uint64_t key = strtoull(q[i].c_str(), &end, 16);
+        if (!end || *end != 0 || q[i].empty()) continue;
+        for (int t = GT_64x64; t <= GT_128x128; ++t)
+            if (q[i + 1] == tile_name(t)) g_tune[key] = t;
+    }
+}
+
+void tune_save_locked()
+{
+    const char* path = getenv("RSVD_TUNE_CACHE");
+    if (!path || !*path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto& kv : g_tune)
+        fprintf(f, "  \"%016llx\": \"%s\"%s\n", (unsigned long long)kv.first, tile_name(kv.second),
+                ++i < g_tune.size() ? "," : "");
+    fprintf(f, "}\n");
+    if (fclose(f) == 0) (void)rename(tmp.c_str(), path);
+}
+
+// One tunable launch of the tuning execute: unless the table knows its
+// signature, time every tile (one warm-up, then the mean of three launches,
+// HIP events on the plan's stream) and keep the fastest.  Every tile computes
+// each output element with the same K order, so the products are identical
+// and repeating a launch (none of these accumulates) leaves the same result.
+int tune_gemm(rsvd_plan& P, const GemmLaunch& g, hipStream_t s)
+{
+    const int np = P.nprob;
+    std::vector<GemmDesc> d0(np);
+    memcpy(d0.data(), P.hb.bytes.data() + g.off_desc, sizeof(GemmDesc) * np);
+    int best = g.tile;
+    bool known;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(g.sig);
+        known = it != g_tune.end();
+        if (known) best = it->second;
+    }
+    auto install = [&](int tile, int* total) -> int {
+        std::vector<GemmDesc> d = d0;
+        std::vector<int> map = item_map(finalize_descs(d, (GemmTile)tile, total));
+        if (map.size() > 2 * (size_t)std::max(g.cap, 1)) return fail(RSVD_ERR_HIP, "tuner: item map exceeds its reservation");
+        map.resize(2 * (size_t)std::max(g.cap, 1), 0);
+        HIPCHK(hipStreamSynchronize(s));  // earlier copies out of the pinned blob are done
+        memcpy(P.hblob_pinned + g.off_desc, d.data(), sizeof(GemmDesc) * np);
+        memcpy(P.hblob_pinned + g.off_begin, map.data(), sizeof(int) * map.size());
+        HIPCHK(hipMemcpyAsync(P.dblob + g.off_desc, P.hblob_pinned + g.off_desc, sizeof(GemmDesc) * np,
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(P.dblob + g.off_begin, P.hblob_pinned + g.off_begin, sizeof(int) * map.size(),
+                              hipMemcpyHostToDevice, s));
+        return RSVD_OK;
+    };
+    auto run = [&](int tile, int total) -> int {
+        if (total <= 0) return RSVD_OK;
+        hipError_t e = launch_gemm(g.kind, g.ea, g.ex, g.ec, (GemmTile)tile, false, dp<GemmDesc>(P, g.off_desc),
+                                   dp<int>(P, g.off_begin), np, total, s);
+        return e == hipSuccess ? RSVD_OK : fail(RSVD_ERR_HIP, std::string("tuner launch: ") + hipGetErrorString(e));
+    };
+    int rc, total = 0;
+    if (!known) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIPCHK(hipEventCreate(&e0));
+        hipError_t he = hipEventCreate(&e1);
+        if (he != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return fail(RSVD_ERR_HIP, std::string("tuner event: ") + hipGetErrorString(he));
+        }
+        float best_ms = 0.f;
+        rc = RSVD_OK;
+        for (int t = GT_64x64; t <= GT_128x128 && rc == RSVD_OK; ++t) {
+            if ((rc = install(t, &total)) != RSVD_OK) break;
+            if ((rc = run(t, total)) != RSVD_OK) break;
+            if ((he = hipEventRecord(e0, s)) != hipSuccess) break;
+            for (int r = 0; r < 3 && rc == RSVD_OK; ++r) rc = run(t, total);
+            if (rc != RSVD_OK) break;
+            if ((he = hipEventRecord(e1, s)) != hipSuccess) break;
+            if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
+            float ms = 0.f;
+            if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            if (t == GT_64x64 || ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != RSVD_OK) return rc;
+        if (he != hipSuccess) return fail(RSVD_ERR_HIP, std::string("tuner timing: ") + hipGetErrorString(he));
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[g.sig] = best;
+        tune_save_locked();
+    }
+    if ((rc = install(best, &total)) != RSVD_OK) return rc;
+    if ((rc = run(best, total)) != RSVD_OK) return rc;
+    if ((int)P.tile_ovr.size() <= g.slot) P.tile_ovr.resize(g.slot + 1, -1);
+    P.tile_ovr[g.slot] = best;
+    return RSVD_OK;
+}
+
+int gemm(rsvd_plan& P, const GemmLaunch& g, hipStream_t s, int cat)
 {
     if (g.total <= 0) return RSVD_OK;
+    if (P.tuner && g.slot >= 0) return tune_gemm(P, g, s);
     PLAUNCH(cat, g.flops,
             launch_gemm(g.kind, g.ea, g.ex, g.ec, g.tile, g.gather, dp<GemmDesc>(P, g.off_desc), dp<int>(P, g.off_begin), P.nprob,
                         g.total, s));
@@ -1294,6 +1507,23 @@ int plan_execute(rsvd_plan* P, const void* const* A, void* const* U, void* const
         ++P->fwd_gen;
     }
     P->fwd_saved = false;
+    if ((P->flags & RSVD_PLAN_TUNE) && !P->tuned && !P->fullsvd) {
+        // one eager execute that times the candidate tiles of every tunable
+        // product on these inputs, then the descriptors with the chosen tiles
+        P->tuner = true;
+        int rc = enqueue(*P, stream);
+        P->tuner = false;
+        if (rc != RSVD_OK) return rc;
+        HIPCHK(hipStreamSynchronize(stream));
+        P->tuned = true;
+        build_blob(*P, A, U, S, VT, w, kk, info);
+        if (P->hb.bytes.size() != P->blob_bytes) return fail(RSVD_ERR_HIP, "descriptor layout changed");
+        memcpy(P->hblob_pinned, P->hb.bytes.data(), P->blob_bytes);
+        HIPCHK(hipMemcpyAsync(P->dblob, P->hblob_pinned, P->blob_bytes, hipMemcpyHostToDevice, stream));
+        HIPCHK(hipEventRecord(P->upload_done, stream));
+        P->upload_pending = true;
+        ++P->fwd_gen;
+    }
     if (P->flags & RSVD_PLAN_GRAPH) {
         if (!P->gexec) {
             HIPCHK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -1628,6 +1858,56 @@ int rsvd_plan_postselect(rsvd_plan_t* plan, int64_t chi, int64_t* chi_s, void* s
 }
 
 int64_t rsvd_plan_workspace_bytes(const rsvd_plan_t* plan) { return plan ? (int64_t)plan->ws_bytes : 0; }
+
+int rsvd_plan_tiles(const rsvd_plan_t* plan, int32_t* tiles, int64_t cap, int64_t* count)
+{
+    g_err.clear();
+    if (!plan || !count || cap < 0 || (cap > 0 && !tiles)) return fail(RSVD_ERR_INVALID, "null argument or negative cap");
+    int64_t c = 0;
+    for (int t : plan->slot_tile) {
+        if (t < 0) continue;
+        if (c < cap) {
+            tiles[2 * c] = gemm_tile_m((GemmTile)t);
+            tiles[2 * c + 1] = gemm_tile_n((GemmTile)t);
+        }
+        ++c;
+    }
+    *count = c;
+    return RSVD_OK;
+}
+
+int rsvd_plan_set_tiles(rsvd_plan_t* plan, const int32_t* tiles, int64_t count)
+{
+    g_err.clear();
+    if (!plan || (count > 0 && !tiles)) return fail(RSVD_ERR_INVALID, "null plan or tiles");
+    int64_t n = 0;
+    for (int t : plan->slot_tile) n += t >= 0;
+    if (count != n) return fail(RSVD_ERR_INVALID, "count must equal the plan's number of tunable products (" +
+                                                      std::to_string(n) + ")");
+    std::vector<int> chosen((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        int t = -1;
+        for (int c = GT_64x64; c <= GT_128x128; ++c)
+            if (gemm_tile_m((GemmTile)c) == tiles[2 * i] && gemm_tile_n((GemmTile)c) == tiles[2 * i + 1]) t = c;
+        if (t < 0) return fail(RSVD_ERR_INVALID, "tile " + std::to_string(i) + " is not 64x64, 128x64, 64x128 or 128x128");
+        chosen[(size_t)i] = t;
+    }
+    HIPCHK(hipDeviceSynchronize());  // no execute of this plan may still use its graph or descriptors
+    plan->tile_ovr.assign(plan->slot_tile.size(), -1);
+    int64_t i = 0;
+    for (size_t slot = 0; slot < plan->slot_tile.size(); ++slot)
+        if (plan->slot_tile[slot] >= 0) {
+            plan->tile_ovr[slot] = chosen[(size_t)i];
+            plan->slot_tile[slot] = chosen[(size_t)i++];
+        }
+    plan->tuned = true;
+    plan->blob_valid = false;  // the next execute rebuilds and uploads the descriptors
+    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    plan->gexec = nullptr;
+    plan->graph = nullptr;
+    return RSVD_OK;
+}
 
 void rsvd_plan_destroy(rsvd_plan_t* plan) { plan_free(plan); }
 

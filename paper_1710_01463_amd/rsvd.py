@@ -114,7 +114,7 @@ class Plan:
     """
 
     def __init__(self, problems, dtype=torch.float64, prec="f64", fullsvd=False, graph=True,
-                 save=False, refine=True, device="cuda"):
+                 save=False, refine=True, tune=False, device="cuda"):
         self.dtype = dtype
         self.device = torch.device(device)
         self.fullsvd = fullsvd
@@ -133,7 +133,8 @@ class Plan:
             arr[i].ldu = 0
             arr[i].ldvt = 0
         flags = (L.PLAN_FULLSVD if fullsvd else 0) | (L.PLAN_GRAPH if graph else 0) | \
-                (L.PLAN_SAVE if save else 0) | (0 if refine else L.PLAN_NO_REFINE)
+                (L.PLAN_SAVE if save else 0) | (0 if refine else L.PLAN_NO_REFINE) | \
+                (L.PLAN_TUNE if tune else 0)
         h = ctypes.c_void_p()
         L.check(L.lib().rsvd_plan_create(arr, n, _DT[dtype], L.PREC[prec], flags, ctypes.byref(h)))
         self._h = h
@@ -145,6 +146,19 @@ class Plan:
                       L.ptr_array([o[1].data_ptr() for o in self.outputs]),
                       L.ptr_array([o[2].data_ptr() for o in self.outputs]))
         self._keep = None
+
+    def tiles(self):
+        """(rows, cols) of the workgroup tile of each tunable forward product, in launch order."""
+        count = ctypes.c_int64()
+        L.check(L.lib().rsvd_plan_tiles(self._h, None, 0, ctypes.byref(count)))
+        buf = (ctypes.c_int32 * max(2 * count.value, 1))()
+        L.check(L.lib().rsvd_plan_tiles(self._h, buf, count.value, ctypes.byref(count)))
+        return [(buf[2 * i], buf[2 * i + 1]) for i in range(count.value)]
+
+    def set_tiles(self, tiles):
+        """Fixes the tile of each tunable forward product (a list as returned by tiles())."""
+        buf = (ctypes.c_int32 * max(2 * len(tiles), 1))(*[v for t in tiles for v in t])
+        L.check(L.lib().rsvd_plan_set_tiles(self._h, buf, len(tiles)))
 
     @property
     def workspace_bytes(self):

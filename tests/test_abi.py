@@ -21,7 +21,7 @@ def test_header_declares_the_boundary():
     for n in ["rsvd_truncate", "fullsvd_truncate", "rsvd_plan_create", "rsvd_plan_execute",
               "rsvd_plan_destroy", "rsvd_last_error", "rsvd_plan_profile", "rsvd_gaussian",
               "rsvd_plan_backward", "rsvd_plan_profile_backward", "rsvd_plan_postselect",
-              "rsvd_truncate_adaptive"]:
+              "rsvd_truncate_adaptive", "rsvd_plan_tiles", "rsvd_plan_set_tiles"]:
         assert n in names
 
 
@@ -82,6 +82,11 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert st == _lib.RSVD_ERR_INVALID
     # post-selection without a plan
     assert lib.rsvd_plan_postselect(None, 4, dummy, None) == _lib.RSVD_ERR_INVALID
+    assert b"plan" in lib.rsvd_last_error()
+    # tile query and tile choice without a plan
+    count = ctypes.c_int64()
+    assert lib.rsvd_plan_tiles(None, None, 0, ctypes.byref(count)) == _lib.RSVD_ERR_INVALID
+    assert lib.rsvd_plan_set_tiles(None, None, 0) == _lib.RSVD_ERR_INVALID
     assert b"plan" in lib.rsvd_last_error()
 
 
