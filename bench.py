@@ -240,11 +240,12 @@ def main():
     plist = [dict(m=pr.m, n=pr.n, k=pr.k, p=pr.p, q=pr.q, seed=pr.seed) for pr in probs]
     plan = P.Plan(plist, dtype, args.prec, graph=True, tune=not args.no_tune)
     heuristic_tiles = plan.tiles()
-    t0 = time.perf_counter()
-    plan.execute(As)  # with tuning: times every tile of each forward product, then executes
-    torch.cuda.synchronize()
-    tune_s = time.perf_counter() - t0
-    log(f"[bench] first execute {tune_s:.2f} s, tiles {plan.tiles()}")
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        plan.execute(As)  # times every tile of each forward product, then executes
+        torch.cuda.synchronize()
+        tune_s = time.perf_counter() - t0
+        log(f"[bench] tuning execute {tune_s:.2f} s, tiles {plan.tiles()}")
 
     log(f"[bench] warmup {args.warmup}")
     for _ in range(args.warmup):
