@@ -174,6 +174,51 @@ def diff_leg(args, P, torch, wl):
     }
 
 
+def precision_leg(args, P, torch, wl):
+    """Mixed precision on the TTN-shaped batch: 16 matrices 1024 x 1024 stored
+    in FP32, s_i = |i^-1.2 (1 + 0.05 xi)|, k = 64, p = 16, q = 3.  The same
+    batch runs with BF16 and with FP32 sketch and power-iteration products
+    (FP64 Cholesky QR, FP64 projection B = Q^T A, FP64 small SVD) and fully in
+    FP64 (the FP32 values upcast).  Reports the step times, the GEMM work
+    rate, the truncation error against the optimum and each mixed form's
+    singular values against the FP64 path's, relative to sigma_1."""
+    import numpy as np
+    W = wl.c3(16)
+    probs = W.problems
+    log(f"[bench] precision leg: generating {len(probs)} matrices 1024x1024")
+    mats = gen_matrices(probs, np.float32)
+    A32 = [torch.from_numpy(A).cuda() for A in mats]
+    A64 = [A.double() for A in A32]
+    plist = [dict(m=pr.m, n=pr.n, k=pr.k, p=pr.p, q=pr.q, seed=pr.seed) for pr in probs]
+    gemm_flops = sum(pr.gemm_flops() for pr in probs)
+    # the optimal discarded weight of each input: the stored FP32 values' own tail
+    tails = [float(np.sum(np.linalg.svd(A.astype(np.float64), compute_uv=False)[pr.k:] ** 2))
+             for A, pr in zip(mats[:2], probs[:2])]
+    out = {"workload": f"C3: {len(probs)} x 1024x1024 FP32 storage, s_i=|i^-1.2 (1+0.05 xi)|, k=64 p=16 q=3"}
+    sig = {}
+    for prec, dtype, As in (("bf16", torch.float32, A32), ("f32", torch.float32, A32), ("f64", torch.float64, A64)):
+        plan = P.Plan(plist, dtype, prec, graph=True)
+        plan.execute(As)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.diff_steps):
+            plan.execute(As)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.diff_steps * 1e3
+        w = plan.w.cpu().numpy()
+        ok = bool(np.all(plan.info.cpu().numpy() == 0))
+        sig[prec] = [o[1].double().cpu().numpy() for o in plan.outputs]
+        plan.close()
+        out[prec] = {"ms": ms, "per_s": len(probs) / (ms / 1e3),
+                     "gemm_tflops": gemm_flops / (ms * 1e-3) / 1e12, "status_ok": ok,
+                     "eps_F_over_delta_EY": [float(np.sqrt(w[b] / tails[b])) for b in range(len(tails))]}
+    for prec in ("bf16", "f32"):
+        out[prec]["max_dsigma_over_s1_vs_f64"] = max(
+            float(np.max(np.abs(a - b)) / b[0]) for a, b in zip(sig[prec], sig["f64"]))
+        out[prec]["speedup_vs_f64"] = out["f64"]["ms"] / out[prec]["ms"]
+    return out
+
+
 def tebd_leg(P, torch, wl):
     """The TEBD compression shapes (Sec. III): 64 product updates (200 x 500,
     ratio 1/2) and 32 block updates (500 x 500, ratio 1/5) at chi = 100, FP64,
@@ -395,6 +440,12 @@ def main():
 
     if not args.no_diff:
         result["differentiation"] = diff_leg(args, P, torch, wl)
+
+    if not args.no_diff:
+        try:
+            result["precision"] = precision_leg(args, P, torch, wl)
+        except Exception as e:  # reported, never fatal to the main line
+            result["precision"] = {"error": repr(e)}
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle leg")
