@@ -1513,7 +1513,12 @@ int plan_execute(rsvd_plan* P, const void* const* A, void* const* U, void* const
         P->tuner = true;
         int rc = enqueue(*P, stream);
         P->tuner = false;
-        if (rc != RSVD_OK) return rc;
+        if (rc != RSVD_OK) {
+            // a candidate's descriptors may be installed: let its copies finish, rebuild on the next execute
+            (void)hipStreamSynchronize(stream);
+            P->blob_valid = false;
+            return rc;
+        }
         HIPCHK(hipStreamSynchronize(stream));
         P->tuned = true;
         build_blob(*P, A, U, S, VT, w, kk, info);
