@@ -152,7 +152,7 @@ def _finish(A, Ufull, sig, Vt_full, k, delta, tail_direct):
     if a2 == 0.0:
         k_kept = 0
     elif delta > 0.0:
-        for kp in range(0, kk + 1):
+        for kp in range(1, kk + 1):
             if weight(kp) <= delta * a2:
                 k_kept = kp
                 break

@@ -63,7 +63,7 @@ def block_krylov_rsvd(A, k, p, q, seed, delta=0.0):
     if a2 == 0.0:
         k_kept = 0
     elif delta > 0.0:
-        for kp in range(kk + 1):
+        for kp in range(1, kk + 1):
             if max(0.0, a2 - _ksum(sig[:kp] ** 2)) <= delta * a2:
                 k_kept = kp
                 break

@@ -62,7 +62,7 @@ def single_view_rsvd(A, k, p, seed, delta=0.0):
     if a2 == 0.0:
         k_kept = 0
     elif delta > 0.0:
-        for kp in range(kk + 1):
+        for kp in range(1, kk + 1):
             if err(kp) <= delta * a2:
                 k_kept = kp
                 break

@@ -138,6 +138,12 @@ def pin_truncation_rule(M):
     assert np.all(r.S[3:] == 0) and np.all(r.U[:, 3:] == 0) and np.all(r.VT[3:] == 0)
     z = M.crsvd(np.zeros((5, 4), dtype=complex), 2, 1, 1, 1)
     assert z.k_kept == 0 and z.w == 0.0
+    # delta >= 1: w(1) <= ||A||^2 always holds, so the smallest k' >= 1 is 1
+    for big in (1.0, 3.0):
+        r1 = M.crsvd(A, 5, 10, 0, 3, delta=big)
+        assert r1.k_kept == 1 and r1.w == pytest.approx(a2 - 1.0, rel=1e-9)
+        f1 = M.cfullsvd(A, 5, delta=big)
+        assert f1.k_kept == 1 and f1.w == pytest.approx(a2 - 1.0, rel=1e-9)
     bad = np.ones((4, 4), dtype=complex)
     bad[1, 2] = np.nan
     assert M.crsvd(bad, 2, 1, 1, 1).status == M.ERR_NONFINITE
@@ -177,6 +183,7 @@ def test_real_input_matches_the_real_oracle():
 # ---------------------------------------------------------------- planted mistakes
 
 MUTATIONS = {
+    "cut_search_from_zero": ("for kp in range(1, kk + 1):", "for kp in range(0, kk + 1):"),
     "B_uses_plain_transpose": ("B = Q.conj().T @ A", "B = Q.T @ A"),
     "no_phase_alignment": ("y = M[:, j] * e.conjugate()", "y = M[:, j] * e"),
     "gaussian_variance_two": ("complex(r * math.cos(t), r * math.sin(t)) / math.sqrt(2.0)",

@@ -67,6 +67,10 @@ def pin_truncation_rule(M):
     assert np.all(r.S[3:] == 0) and np.all(r.U[:, 3:] == 0)
     z = M.block_krylov_rsvd(np.zeros((6, 5)), 2, 1, 1, 1)
     assert z.k_kept == 0 and z.w == 0.0
+    # delta >= 1: w(1) <= ||A||^2 always holds, so the smallest k' >= 1 is 1
+    for big in (1.0, 3.0):
+        r1 = M.block_krylov_rsvd(A, 5, 1, 1, 2, delta=big)
+        assert r1.k_kept == 1 and r1.w == pytest.approx(float(np.sum(s[1:] ** 2)), rel=1e-9)
 
 
 PINS = [pin_q0_is_the_rsvd, pin_full_space_is_exact, pin_never_worse_than_rsvd, pin_invariants,
@@ -90,6 +94,7 @@ def test_krylov_beats_rsvd_at_equal_passes_on_a_flat_spectrum():
 
 
 MUTATIONS = {
+    "cut_search_from_zero": ("for kp in range(1, kk + 1):", "for kp in range(0, kk + 1):"),
     "basis_from_last_block_only": ("Q, _ = hqr(np.concatenate(blocks, axis=1)[:, :L])", "Q = blocks[-1]"),
     "power_step_without_transpose": ("Z, _ = hqr(A.T @ Qj)", "Z, _ = hqr(A @ Qj)"),
     "weight_from_all_values": ("w = max(0.0, a2 - _ksum(sig[:k_kept] ** 2))", "w = max(0.0, a2 - _ksum(sig ** 2))"),

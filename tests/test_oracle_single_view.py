@@ -76,6 +76,10 @@ def pin_truncation_rule(M):
     assert np.all(r.S[3:] == 0) and np.all(r.VT[3:] == 0)
     z = M.single_view_rsvd(np.zeros((7, 6)), 2, 1, 1)
     assert z.k_kept == 0 and z.w == 0.0
+    # delta >= 1: w(1) <= ||A||^2 always holds, so the smallest k' >= 1 is 1
+    for big in (1.0, 3.0):
+        r1 = M.single_view_rsvd(A, 5, 3, 4, delta=big)
+        assert r1.k_kept == 1 and r1.w == pytest.approx(float(np.sum(s[1:] ** 2)), rel=1e-8)
 
 
 PINS = [pin_exact_on_low_rank, pin_bounded_by_two_pass_and_optimum, pin_expected_error_over_psi,
@@ -88,6 +92,7 @@ def test_single_view_oracle_pin(pin):
 
 
 MUTATIONS = {
+    "cut_search_from_zero": ("for kp in range(1, kk + 1):", "for kp in range(0, kk + 1):"),
     "psi_shares_omega_key": ("Psi = gaussian(seed ^ (1 << 63), m, s).T", "Psi = gaussian(seed, m, s).T"),
     "x_without_psi_q_inverse": ("X = np.linalg.solve(R2, Q2.T @ W)", "X = Q2.T @ W"),
     "co_range_too_narrow": ("s = min(2 * l + 1, m)", "s = min(l + 2, m)"),
