@@ -14,8 +14,9 @@
  *  - Matrices are row-major with an explicit leading dimension in elements.
  *  - All matrix, vector and scalar-output pointers are DEVICE pointers owned
  *    by the caller; the library never frees them.  Library-owned device
- *    memory lives only inside an rsvd_plan_t (workspace, descriptors, graph)
- *    or in the small plan cache of the one-shot calls.
+ *    memory lives only inside an rsvd_plan_t (workspace, descriptors, graph),
+ *    in the small plan cache of the one-shot calls, or in the static scratch
+ *    array of rsvd_truncate_noalloc.
  *  - stream is a hipStream_t passed as void* (NULL = the null stream).
  *  - k is clamped to min(m, n) (small symmetry sectors routinely ask for more
  *    triplets than the block has).  l = min(k + p, m, n).
@@ -89,6 +90,34 @@ int rsvd_truncate(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t 
                   int64_t p, int64_t q, uint64_t seed, double delta_trunc, rsvd_prec_t prec, void* U,
                   int64_t ldu, void* S, void* VT, int64_t ldvt, double* discarded_weight,
                   int64_t* k_kept, void* stream);
+
+/*
+ * rsvd_truncate_noalloc -- rsvd_truncate for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  Same arguments, arithmetic and results
+ * as rsvd_truncate (bit for bit: the same kernels run in the same order),
+ * with these differences:
+ *  - Nothing is allocated.  The workspace and the descriptor tables of the
+ *    call live in one static device array of RSVD_NOALLOC_SCRATCH_BYTES per
+ *    GPU, held by the library from load until the process ends.  A problem
+ *    whose workspace and descriptors do not fit returns RSVD_ERR_INVALID
+ *    before any device work (512 x 512 at k + p = 272 needs about 10 MiB;
+ *    2048 x 2048 at k + p = 256 about 33 MiB).
+ *  - Asynchronous on stream: no graph, no plan cache, no synchronisation.
+ *    info (device int, may be NULL) receives the status of the factorisation
+ *    (RSVD_OK, RSVD_ERR_NONFINITE or RSVD_ERR_NOCONV); the return value only
+ *    reports argument and launch errors.
+ *  - Every call on one GPU shares that GPU's scratch array, which keeps the
+ *    last call's contents.  Calls whose executions overlap on one GPU (on
+ *    different streams or from different threads) race and must be ordered
+ *    by the caller.  The descriptors are passed by value in the call's
+ *    launches, so a graph captured around one call replays that call.
+ */
+#define RSVD_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+int rsvd_truncate_noalloc(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t lda, int64_t k,
+                          int64_t p, int64_t q, uint64_t seed, double delta_trunc, rsvd_prec_t prec, void* U,
+                          int64_t ldu, void* S, void* VT, int64_t ldvt, double* discarded_weight,
+                          int64_t* k_kept, int* info, void* stream);
 
 /*
  * rsvd_truncate_adaptive -- fixed-error truncation with an adaptive rank (the

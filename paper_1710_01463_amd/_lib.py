@@ -50,6 +50,10 @@ def lib():
                                     ctypes.c_uint64, ctypes.c_double, ctypes.c_int, _vp, _i64, _vp,
                                     _vp, _i64, _vp, _vp, _vp]
         L.rsvd_truncate.restype = ctypes.c_int
+        L.rsvd_truncate_noalloc.argtypes = [_vp, ctypes.c_int, _i64, _i64, _i64, _i64, _i64, _i64,
+                                            ctypes.c_uint64, ctypes.c_double, ctypes.c_int, _vp, _i64, _vp,
+                                            _vp, _i64, _vp, _vp, _vp, _vp]
+        L.rsvd_truncate_noalloc.restype = ctypes.c_int
         L.rsvd_truncate_adaptive.argtypes = [_vp, ctypes.c_int, _i64, _i64, _i64, _i64, _i64, _i64, _i64,
                                              ctypes.c_uint64, ctypes.c_double, ctypes.c_int, _vp, _i64, _vp,
                                              _vp, _i64, _vp, _vp, ctypes.POINTER(ctypes.c_int), _vp]

@@ -188,6 +188,12 @@ hipError_t launch_omega(const OmegaDesc* d, const int* blk_begin, int nprob, int
 
 hipError_t launch_philox_words(const uint32_t* in, uint32_t* out, int64_t count, hipStream_t s);
 
+// Copies `bytes` host bytes from src to device memory dst on stream s, in
+// chunks of UPLOAD_CHUNK_BYTES passed by value as kernel arguments (no
+// staging allocation; src may be reused as soon as the call returns).
+constexpr int UPLOAD_CHUNK_BYTES = 2048;
+hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
+
 // Fill helpers (graph-safe replacements for memset).
 hipError_t launch_fill_i32(int* p, int value, int64_t count, hipStream_t s);
 // Copy A (m x n, lda, any elem) into X as FP64, transposed or not, for the full SVD.

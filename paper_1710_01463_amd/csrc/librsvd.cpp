@@ -1376,11 +1376,25 @@ void plan_free(rsvd_plan* P)
     delete P;
 }
 
-int plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsvd_prec_t prec, unsigned flags,
-                rsvd_plan** out)
+// Kernel attributes set once per process (dynamic LDS limits).
+int kernels_ready()
 {
-    if (!out) return fail(RSVD_ERR_INVALID, "plan output pointer is null");
-    *out = nullptr;
+    static std::once_flag once;
+    static hipError_t init_err = hipSuccess;
+    std::call_once(once, [] {
+        init_err = init_qr_kernels();
+        if (init_err == hipSuccess) init_err = init_select_kernels();
+    });
+    if (init_err != hipSuccess) return fail(RSVD_ERR_HIP, std::string("kernel attributes: ") + hipGetErrorString(init_err));
+    return RSVD_OK;
+}
+
+// Validates the problems and fills the host side of a plan: per-problem
+// sizes, Jacobi blocking and the workspace layout (P.ws_bytes).  No device
+// memory is touched.
+int plan_setup(rsvd_plan* P, const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsvd_prec_t prec,
+               unsigned flags)
+{
     if (!probs || batch < 1 || batch > (1 << 20)) return fail(RSVD_ERR_INVALID, "batch must be in [1, 2^20]");
     if (dt != RSVD_F64 && dt != RSVD_F32) return fail(RSVD_ERR_INVALID, "unknown dtype");
     if (prec != RSVD_PREC_F64 && prec != RSVD_PREC_F32 && prec != RSVD_PREC_BF16)
@@ -1390,7 +1404,6 @@ int plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsv
         int rc = validate_problem(probs[b], fullsvd);
         if (rc != RSVD_OK) return fail(rc, "problem " + std::to_string(b) + ": " + g_err);
     }
-    rsvd_plan* P = new rsvd_plan();
     P->nprob = (int)batch;
     P->dt = dt;
     P->prec = fullsvd ? RSVD_PREC_F64 : prec;
@@ -1440,17 +1453,20 @@ int plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsv
     }
     if (!fullsvd) P->max_sweeps = P->max_l > JAC_WIDE_L ? JAC_MAX_SWEEPS_RSVD_WIDE : JAC_MAX_SWEEPS_RSVD;
     layout(*P);
-    {
-        static std::once_flag once;
-        static hipError_t init_err = hipSuccess;
-        std::call_once(once, [] {
-            init_err = init_qr_kernels();
-            if (init_err == hipSuccess) init_err = init_select_kernels();
-        });
-        if (init_err != hipSuccess) {
-            plan_free(P);
-            return fail(RSVD_ERR_HIP, std::string("kernel attributes: ") + hipGetErrorString(init_err));
-        }
+    return RSVD_OK;
+}
+
+int plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsvd_prec_t prec, unsigned flags,
+                rsvd_plan** out)
+{
+    if (!out) return fail(RSVD_ERR_INVALID, "plan output pointer is null");
+    *out = nullptr;
+    rsvd_plan* P = new rsvd_plan();
+    int rc = plan_setup(P, probs, batch, dt, prec, flags);
+    if (rc == RSVD_OK) rc = kernels_ready();
+    if (rc != RSVD_OK) {
+        plan_free(P);
+        return rc;
     }
     hipError_t e = hipMalloc(&P->ws, P->ws_bytes);
     if (e != hipSuccess) {
@@ -1641,7 +1657,105 @@ int one_shot(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t lda, 
 
 }  // namespace
 
+// ---------------------------------------------------------------- allocation-free one-shot
+// Device memory of rsvd_truncate_noalloc: the workspace of one problem
+// followed by its descriptor tables.  Each GPU holds its own copy of this
+// array from the time the library is loaded until the process ends.
+static __device__ __align__(256) char scratch[RSVD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch;  // device -> address of that device's scratch
+
+// The device address of the current device's scratch, taken once per device
+// with that device current.  In host code the array's name is a stand-in, not
+// a device address; only this pointer is passed to kernels.
+int scratch_address(int dev, char** out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it == g_scratch.end()) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(RSVD_ERR_HIP, "scratch symbol has no device address");
+        it = g_scratch.emplace(dev, (char*)ptr).first;
+    }
+    *out = it->second;
+    return RSVD_OK;
+}
+
+int noalloc_truncate(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t lda, int64_t k, int64_t p,
+                     int64_t q, uint64_t seed, double delta, rsvd_prec_t prec, void* U, int64_t ldu, void* S,
+                     void* VT, int64_t ldvt, double* w, int64_t* kk, int* info, hipStream_t stream)
+{
+    if (!A || !U || !S || !VT || !w || !kk) return fail(RSVD_ERR_INVALID, "null pointer argument");
+    if (dt != RSVD_F64 && dt != RSVD_F32) return fail(RSVD_ERR_INVALID, "unknown dtype");
+    if (prec != RSVD_PREC_F64 && prec != RSVD_PREC_F32 && prec != RSVD_PREC_BF16)
+        return fail(RSVD_ERR_INVALID, "unknown precision");
+    rsvd_problem_t pr;
+    pr.m = m;
+    pr.n = n;
+    pr.lda = lda;
+    pr.k = k;
+    pr.p = p;
+    pr.q = q;
+    pr.seed = seed;
+    pr.delta_trunc = delta;
+    pr.ldu = ldu;
+    pr.ldvt = ldvt;
+    int rc = validate_problem(pr, false);
+    if (rc != RSVD_OK) return rc;
+    if (ldu < std::min(k, std::min(m, n))) return fail(RSVD_ERR_INVALID, "ldu < k");
+    if (ldvt < n) return fail(RSVD_ERR_INVALID, "ldvt < n");
+    // the host side of a one-problem plan, without graph, tuning or saved forward
+    rsvd_plan P;
+    if ((rc = plan_setup(&P, &pr, 1, dt, prec, 0u)) != RSVD_OK) return rc;
+    const size_t ws = align_up(P.ws_bytes, 256);
+    if (ws > (size_t)RSVD_NOALLOC_SCRATCH_BYTES)
+        return fail(RSVD_ERR_INVALID, "problem needs " + std::to_string(ws) + " bytes of workspace; the scratch holds " +
+                                          std::to_string((long long)RSVD_NOALLOC_SCRATCH_BYTES));
+    if ((rc = kernels_ready()) != RSVD_OK) return rc;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    char* base = nullptr;
+    if ((rc = scratch_address(dev, &base)) != RSVD_OK) return rc;
+    P.ws = base;
+    const void* Aa[1] = {A};
+    void* Ua[1] = {U};
+    void* Sa[1] = {S};
+    void* Va[1] = {VT};
+    build_blob(P, Aa, Ua, Sa, Va, w, kk, info);
+    P.blob_bytes = P.hb.bytes.size();
+    if (ws + P.blob_bytes > (size_t)RSVD_NOALLOC_SCRATCH_BYTES) {
+        P.ws = nullptr;
+        return fail(RSVD_ERR_INVALID, "problem needs " + std::to_string(ws + P.blob_bytes) +
+                                          " bytes of workspace and descriptors; the scratch holds " +
+                                          std::to_string((long long)RSVD_NOALLOC_SCRATCH_BYTES));
+    }
+    P.dblob = base + ws;
+    hipError_t e = launch_upload(P.dblob, P.hb.bytes.data(), P.blob_bytes, stream);
+    if (e == hipSuccess) rc = enqueue(P, stream);
+    else rc = fail(RSVD_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
+    // the scratch is not the plan's to free
+    P.ws = nullptr;
+    P.dblob = nullptr;
+    return rc;
+}
+
+}  // namespace
+
 extern "C" {
+
+int rsvd_truncate_noalloc(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t lda, int64_t k, int64_t p,
+                          int64_t q, uint64_t seed, double delta_trunc, rsvd_prec_t prec, void* U, int64_t ldu,
+                          void* S, void* VT, int64_t ldvt, double* discarded_weight, int64_t* k_kept, int* info,
+                          void* stream)
+{
+    g_err.clear();
+    return noalloc_truncate(A, dt, m, n, lda, k, p, q, seed, delta_trunc, prec, U, ldu, S, VT, ldvt,
+                            discarded_weight, k_kept, info, (hipStream_t)stream);
+}
 
 int rsvd_truncate(const void* A, rsvd_dtype_t dt, int64_t m, int64_t n, int64_t lda, int64_t k, int64_t p,
                   int64_t q, uint64_t seed, double delta_trunc, rsvd_prec_t prec, void* U, int64_t ldu, void* S,

@@ -1,4 +1,6 @@
 // Input staging, the Gaussian test matrix, and small fills.
+#include <cstring>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "philox.hpp"
@@ -149,6 +151,31 @@ hipError_t launch_fill_i32(int* p, int value, int64_t count, hipStream_t s)
     hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, value,
                        count);
     return hipGetLastError();
+}
+
+// Host bytes to device memory through kernel arguments: each launch carries
+// one chunk by value, so the copy needs no pinned staging buffer and a
+// captured graph keeps the bytes of the call that recorded it.
+struct UploadChunk {
+    unsigned char bytes[UPLOAD_CHUNK_BYTES];
+};
+
+__global__ __launch_bounds__(256) void upload_kernel(unsigned char* dst, UploadChunk c, int nbytes)
+{
+    for (int i = threadIdx.x; i < nbytes; i += 256) dst[i] = c.bytes[i];
+}
+
+hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s)
+{
+    UploadChunk c;
+    for (size_t off = 0; off < bytes; off += UPLOAD_CHUNK_BYTES) {
+        const size_t nb = bytes - off < (size_t)UPLOAD_CHUNK_BYTES ? bytes - off : (size_t)UPLOAD_CHUNK_BYTES;
+        memcpy(c.bytes, (const unsigned char*)src + off, nb);
+        hipLaunchKernelGGL(upload_kernel, dim3(1), dim3(256), 0, s, (unsigned char*)dst + off, c, (int)nb);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // X = A (m x n) or A^T (n x m) in FP64; 64 x 64 tiles through LDS.

@@ -56,6 +56,30 @@ def rsvd_truncate(A, k, p=10, q=2, seed=0, delta=0.0, prec="f64"):
     return U, S, VT, w, kk
 
 
+def rsvd_truncate_noalloc(A, k, p=10, q=2, seed=0, delta=0.0, prec="f64", out=None):
+    """rsvd_truncate without device allocation inside the library
+    (rsvd_truncate_noalloc): the call runs asynchronously on the current
+    stream in the library's static scratch array.  out: optional
+    (U, S, VT, w, k_kept, info) tensors to write into (needed under graph
+    capture, where this wrapper must not allocate either).  Returns
+    (U, S, VT, w, k_kept, info) without synchronising; info (int32 [1])
+    receives the factorisation's status."""
+    A = _check_matrix(A)
+    m, n = A.shape
+    if out is None:
+        U, S, VT = _outputs(m, n, k, A.dtype, A.device)
+        w = torch.empty(1, dtype=torch.float64, device=A.device)
+        kk = torch.empty(1, dtype=torch.int64, device=A.device)
+        info = torch.empty(1, dtype=torch.int32, device=A.device)
+    else:
+        U, S, VT, w, kk, info = out
+    L.check(L.lib().rsvd_truncate_noalloc(A.data_ptr(), _DT[A.dtype], m, n, A.stride(0), k, p, q,
+                                          ctypes.c_uint64(seed), float(delta), L.PREC[prec], U.data_ptr(),
+                                          U.stride(0), S.data_ptr(), VT.data_ptr(), VT.stride(0), w.data_ptr(),
+                                          kk.data_ptr(), info.data_ptr(), _stream()))
+    return U, S, VT, w, kk, info
+
+
 def rsvd_truncate_adaptive(A, k0, k_max, delta, p=10, q=2, seed=0, prec="f64"):
     """Fixed-error truncation (rsvd_truncate_adaptive): rank k0, 2 k0, ... up to
     k_max until the delta cut binds.  Returns (U, S, VT, w, k_kept, attempts)

@@ -21,7 +21,7 @@ def test_header_declares_the_boundary():
     for n in ["rsvd_truncate", "fullsvd_truncate", "rsvd_plan_create", "rsvd_plan_execute",
               "rsvd_plan_destroy", "rsvd_last_error", "rsvd_plan_profile", "rsvd_gaussian",
               "rsvd_plan_backward", "rsvd_plan_profile_backward", "rsvd_plan_postselect",
-              "rsvd_truncate_adaptive", "rsvd_plan_tiles", "rsvd_plan_set_tiles"]:
+              "rsvd_truncate_adaptive", "rsvd_plan_tiles", "rsvd_plan_set_tiles", "rsvd_truncate_noalloc"]:
         assert n in names
 
 
@@ -83,6 +83,16 @@ def test_invalid_arguments_are_rejected_without_a_device():
     # post-selection without a plan
     assert lib.rsvd_plan_postselect(None, 4, dummy, None) == _lib.RSVD_ERR_INVALID
     assert b"plan" in lib.rsvd_last_error()
+    # allocation-free one-shot: argument checks and the scratch bound come before any device call
+    st = lib.rsvd_truncate_noalloc(None, 0, 10, 10, 10, 2, 2, 1, ctypes.c_uint64(1), 0.0, 0, dummy, 2, dummy,
+                                   dummy, 10, dummy, dummy, None, None)
+    assert st == _lib.RSVD_ERR_INVALID
+    st = lib.rsvd_truncate_noalloc(dummy, 0, 10, 10, 10, 0, 2, 1, ctypes.c_uint64(1), 0.0, 0, dummy, 2, dummy,
+                                   dummy, 10, dummy, dummy, None, None)
+    assert st == _lib.RSVD_ERR_INVALID and b"k" in lib.rsvd_last_error()
+    st = lib.rsvd_truncate_noalloc(dummy, 0, 4096, 4096, 4096, 1000, 24, 2, ctypes.c_uint64(1), 0.0, 0, dummy,
+                                   1000, dummy, dummy, 4096, dummy, dummy, None, None)
+    assert st == _lib.RSVD_ERR_INVALID and b"scratch" in lib.rsvd_last_error()
     # tile query and tile choice without a plan
     count = ctypes.c_int64()
     assert lib.rsvd_plan_tiles(None, None, 0, ctypes.byref(count)) == _lib.RSVD_ERR_INVALID
