@@ -6,8 +6,10 @@ full sketch width, against the full-SVD reference gradient.
 Tolerances (max-norm relative to max |dA|): FP64 1e-9.  The adjoint divides
 by s_j^2 - s_i^2 and by the pivots of every R, so forward rounding differences
 of order 1e-15 grow by the conditioning of those quantities; the spectra here
-keep that growth below 1e4.  FP32 storage with FP32 sketch products: 2e-4, the
-forward's bases differing from FP64 ones at the 1e-6 level.
+keep that growth below 1e4.  FP32 storage with FP32 sketch products: 2e-5
+(measured 4e-7 on the case below: the forward's bases differ from the FP64
+ones at the FP32 rounding level, which the adjoint's divisions by singular
+value gaps amplify by less than 1e2 on this spectrum).
 """
 import numpy as np
 import pytest
@@ -175,7 +177,7 @@ def test_backward_f32_sketch(lib):
     ref = oracle.rsvd_backward(A, k, p, q, pr["seed"], *cot)
     err = relerr(got[0], ref)
     print(f"f32: {err:.2e}")
-    assert err <= 2e-4, err
+    assert err <= 2e-5, err
 
 
 def test_autograd_function_batch(lib):

@@ -117,22 +117,7 @@ def test_c3_full_batch_bf16(lib):
 
 
 def c4_matrix_device(m, n, s, seed):
-    """Seeded m x n FP32 matrix with exact singular values s: diag(s) mixed by
-    three Householder reflections on each side, built on the device (the Haar
-    construction of 512 matrices up to 2048^2 would take minutes on the host)."""
-    g = torch.Generator(device="cuda")
-    g.manual_seed(seed)
-    A = torch.zeros((m, n), dtype=torch.float64, device="cuda")
-    r = len(s)
-    A[torch.arange(r), torch.arange(r)] = torch.from_numpy(s).cuda()
-    for _ in range(3):
-        u = torch.randn(m, generator=g, dtype=torch.float64, device="cuda")
-        u /= u.norm()
-        A -= 2.0 * torch.outer(u, u @ A)
-        v = torch.randn(n, generator=g, dtype=torch.float64, device="cuda")
-        v /= v.norm()
-        A -= 2.0 * torch.outer(A @ v, v)
-    return A.float().contiguous()
+    return wl.c4_matrix_device(m, n, s, seed, torch)
 
 
 def test_c4_full_uneven_batch_f32(lib):
@@ -145,22 +130,37 @@ def test_c4_full_uneven_batch_f32(lib):
     assert np.all(info == 0), np.nonzero(info)
     for b, (U, S, VT) in enumerate(outs):
         check_properties(As[b], U, S, VT, w[b], kk[b], min(probs[b].k, probs[b].m, probs[b].n), 1e-10, 1e-4, 1e-6)
-    # the oracle on the smallest problems and a few mid-sized ones
+    # the oracle on the smallest problems, a few mid-sized ones, the two
+    # cheapest with l >= 288 (30-sweep cap, 18 row blocks and more), and
+    # problems with n >= 1800 and m >= 1800
     cost = np.array([pr.m * pr.n * pr.l for pr in probs])
     order = np.argsort(cost)
-    sample = list(order[:5]) + [order[len(order) // 4], order[len(order) // 3]]
+    wide = sorted((b for b, pr in enumerate(probs) if pr.l >= 288), key=lambda b: cost[b])[:2]
+    sample = list(order[:5]) + [order[len(order) // 4], order[len(order) // 3]] + wide + [8, 310, 2]
+    assert probs[8].n >= 1800 and probs[310].n >= 1800 and probs[2].m >= 1800
+    A64s = {b: As[b].double().cpu().numpy() for b in sample}
+    with ThreadPoolExecutor(8) as ex:  # the oracle calls release the GIL
+        refs = dict(zip(sample, ex.map(lambda b: oracle.rsvd(A64s[b], probs[b].k, probs[b].p, probs[b].q,
+                                                             probs[b].seed, probs[b].delta), sample)))
     for b in sample:
         pr = probs[b]
-        A64 = As[b].double().cpu().numpy()
-        ref = oracle.rsvd(A64, pr.k, pr.p, pr.q, pr.seed, pr.delta)
+        ref = refs[b]
         S = outs[b][1].double().cpu().numpy()
-        tot = np.sum(A64 ** 2)
+        tot = np.sum(A64s[b] ** 2)
         if kk[b] != ref.k_kept:  # the cut sits on the threshold
             assert abs(ref.w / tot - 1e-10) < 1e-11, (b, kk[b], ref.k_kept)
             continue
-        err = np.max(np.abs(S - ref.S)) / ref.S[0]
-        print(f"C4 problem {b} {pr.m}x{pr.n} l={pr.l}: k_kept={ref.k_kept} max|dS|/s1={err:.2e}")
-        assert err <= 1e-7, (b, err)
+        d = np.abs(S - ref.S)
+        err = np.max(d) / ref.S[0]
+        i = int(np.argmax(d))
+        print(f"C4 problem {b} {pr.m}x{pr.n} l={pr.l}: k_kept={ref.k_kept} max|dS|/s1={err:.2e} "
+              f"at i={i} (s_i/s_1={ref.S[i] / ref.S[0]:.2f}, |dS_i|/s_i={d[i] / ref.S[i]:.2e})")
+        # FP32 sketch products on these nearly flat exponential spectra: the
+        # rounding of the products perturbs the sampled subspace at about
+        # u32 = 6e-8 in directions that the q = 2 power steps do not damp, and
+        # that perturbation reaches sigma_i at first order (|d sigma_i| ~ u32
+        # sigma_i); the FP64 pass B = Q^T A cannot remove it.  Bar 2 u32 s_1.
+        assert err <= 2 * 2.0 ** -24, (b, err)
     plan.close()
 
 
@@ -195,5 +195,7 @@ def test_c5_full_batch_forward_and_adjoint(lib):
     err_g = np.max(np.abs(g - g_ref)) / np.max(np.abs(g_ref))
     print(f"C5 problem {b}: max|dS|/s1 = {err_s:.2e}, max|d dA|/max|dA| = {err_g:.2e}")
     assert err_s <= 1e-8
-    assert err_g <= 1e-3
+    # measured 8.5e-5: the FP32 forward's rounding reaches the gradient through the
+    # broadened 1 / (s_j^2 - s_i^2) factors of the three pairs (up to 1 / (2 sqrt(eps)))
+    assert err_g <= 3e-4
     plan.close()

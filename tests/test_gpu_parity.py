@@ -168,7 +168,11 @@ def test_zero_and_nonfinite(lib):
 
 
 # ---------------------------------------------------------------- full SVD
-@pytest.mark.parametrize("m,n,k", [(64, 64, 20), (100, 37, 30), (37, 100, 30), (150, 150, 150), (5, 3, 2)])
+# 300^2, 512 x 280 and 280 x 512 have 19 and 18 row blocks of 16: from 16 blocks
+# on the Jacobi rounds 2.. of a sweep rotate only the cross-block row pairs,
+# the schedule the benchmark's 500^2 and 512^2 full SVDs run
+@pytest.mark.parametrize("m,n,k", [(64, 64, 20), (100, 37, 30), (37, 100, 30), (150, 150, 150), (5, 3, 2),
+                                   (300, 300, 120), (512, 280, 280), (280, 512, 200)])
 def test_fullsvd_matches_oracle(lib, m, n, k):
     s = wl.spectrum_power(min(m, n), 1.0)
     A = wl.make_matrix(m, n, s, seed=51)
@@ -216,3 +220,28 @@ def test_graph_replays_are_identical(lib):
         assert np.array_equal(S, first)
     ref = oracle.rsvd(host(A), 20, 10, 2, 3)
     assert np.all(np.abs(first - ref.S) <= sigma_tol_f64(ref.S))
+
+
+def test_persistent_jacobi_equals_round_launches(lib):
+    """Small plans run the Jacobi phase as one persistent launch; the same plan
+    with one launch per round must give bit-identical outputs (same rotations
+    in the same order per problem), for the RSVD, the triangular-factor path,
+    FP32 storage and the full SVD."""
+    shapes = [(100, 80, 20, 8, 2), (40, 200, 12, 6, 1), (130, 257, 33, 8, 2), (64, 64, 64, 0, 1), (33, 17, 5, 3, 0),
+              (90, 700, 24, 8, 2)]  # the last one takes the triangular-factor path (n >= 4 l)
+    mats = [wl.make_matrix(m, n, wl.spectrum_exp(min(m, n), 0.04 + 0.02 * i), seed=90 + i)
+            for i, (m, n, _, _, _) in enumerate(shapes)]
+    probs = [dict(m=m, n=n, k=k, p=p, q=q, seed=95 + i) for i, (m, n, k, p, q) in enumerate(shapes)]
+    for dtype, full in ((torch.float64, False), (torch.float32, False), (torch.float64, True)):
+        As = [dev(A, dtype) for A in mats]
+        pl = [dict(m=pr["m"], n=pr["n"], k=pr["k"]) for pr in probs] if full else probs
+        res = []
+        for rl in (False, True):
+            plan = lib.Plan(pl, dtype, "f64", fullsvd=full, graph=True, round_launches=rl)
+            outs, w, kk, info = plan.execute(As)
+            torch.cuda.synchronize()
+            assert int(info.abs().sum()) == 0
+            res.append(([t.clone() for o in outs for t in o], w.clone(), kk.clone()))
+            plan.close()
+        (a, wa, ka), (b, wb, kb) = res
+        assert all(torch.equal(x, y) for x, y in zip(a, b)) and torch.equal(wa, wb) and torch.equal(ka, kb), (dtype, full)

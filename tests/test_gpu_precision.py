@@ -1,12 +1,17 @@
 """GPU parity of the mixed-precision paths and of uneven batches.
 
 Tolerances on singular values are relative to sigma_1:
-  FP32 sketch/power products:  <= 1e-6 before refinement, <= 1e-8 after;
-  BF16 sketch/power products:  <= 1e-3 before refinement; after the single
-  FP64 refinement pass of B = Q^T A the reachable bound is about 1e-6 (the
-  remaining error enters at first order through the residual of the BF16
-  subspace), so the test asserts 2e-5 there and the design notes record the
-  miss of 1e-8.
+  FP32 sketch/power products:  <= 1e-6 before refinement, <= 1e-8 after on
+  decaying spectra.  On nearly flat spectra (the exponential ones with small
+  alpha) the power steps do not damp the directions the FP32 rounding of the
+  products perturbs, and the singular values of B = Q^T A depend on the
+  sampled subspace at first order: |d sigma_i| ~ u32 sigma_i (u32 = 2^-24),
+  which no FP64 pass over the same subspace removes; the bar there is
+  2 u32 sigma_1.
+  BF16 sketch/power products:  <= 1e-3 before refinement; after the FP64
+  refinement pass of B the same first-order mechanism leaves about 1e-6
+  sigma_1 at the last kept index (the leading quarter of the kept values
+  sits near 5e-8), so the bar is 2e-5 and 1e-8 is not reached.
 The FP64 oracle runs on the exact FP32-stored matrix, upcast.
 """
 import numpy as np
@@ -107,8 +112,8 @@ def test_uneven_batch_f32(lib):
     """FP32 sketch on the uneven exponential-spectrum batch.  Where alpha is
     small the spectrum is nearly flat over the sketched range and the RSVD's
     singular values depend on the sampled subspace at first order, so the FP32
-    rounding of that subspace reaches them: measured up to ~3e-8 sigma_1 here,
-    bound 1e-7 (the 1e-8 bar holds on the decaying spectra above)."""
+    rounding of that subspace reaches them at about u32 sigma_i: bar 2 u32
+    sigma_1 (the 1e-8 bar holds on the decaying spectra above)."""
     mats, probs = c4_like(24, 4, 320)
     res, w, kk, info = run_plan(lib, mats, probs, torch.float32, "f32")
     assert np.all(info == 0), info
@@ -124,7 +129,7 @@ def test_uneven_batch_f32(lib):
         kept = ref.k_kept
         err = np.max(np.abs(S[:kept] - ref.S[:kept])) / ref.S[0]
         print(f"problem {i}: {pr['m']}x{pr['n']} k={pr['k']} kept={kept} max|dS|/s1={err:.2e}")
-        assert err <= 1e-7, (i, err)
+        assert err <= 2 * 2.0 ** -24, (i, err)
         assert np.all(S[kept:] == 0)
         assert abs(w[i] - ref.w) <= 1e-8 * tot, (i, w[i], ref.w)
         assert np.linalg.norm(U[:, :kept].T @ U[:, :kept] - np.eye(kept)) < 1e-5

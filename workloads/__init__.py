@@ -33,6 +33,24 @@ def haar_frame(rng: np.random.Generator, m: int, r: int) -> np.ndarray:
     return q * d
 
 
+def haar_unitary_frame(rng: np.random.Generator, m: int, r: int) -> np.ndarray:
+    """m x r complex matrix with orthonormal columns, Haar distributed (thin QR
+    of a circular complex Gaussian with the phases of diag(R) absorbed)."""
+    g = (rng.standard_normal((m, r)) + 1j * rng.standard_normal((m, r))) / math.sqrt(2.0)
+    q, rr = np.linalg.qr(g)
+    d = np.diag(rr)
+    d = np.where(d == 0, 1.0, d / np.where(d == 0, 1.0, np.abs(d)))
+    return q * d
+
+
+def make_complex_matrix(m: int, n: int, s: np.ndarray, seed: int) -> np.ndarray:
+    """A = U diag(s) V^H with Haar unitary frames, complex128."""
+    rng = np.random.default_rng(seed)
+    U = haar_unitary_frame(rng, m, len(s))
+    V = haar_unitary_frame(rng, n, len(s))
+    return (U * s) @ V.conj().T
+
+
 def make_matrix(m: int, n: int, s: np.ndarray, seed: int) -> np.ndarray:
     """A = U diag(s) V^T, U (m x r), V (n x r), r = len(s) <= min(m, n), FP64."""
     rng = np.random.default_rng(seed)
@@ -188,6 +206,27 @@ def tebd_block(batch: int = 32, chi: int = 100, d: int = 5) -> Workload:
     probs = [Problem(m, m, chi, 10, 2, 2000 * 7 + b, 1000 * 7 + b, s) for b in range(batch)]
     return Workload("TEBD-B", f"{batch} x {m}x{m} (chi={chi}, d={d}), s_i = i^-2, k={chi} p=10 q=2",
                     probs, "f64", ("f64",))
+
+
+def c4_matrix_device(m: int, n: int, s: np.ndarray, seed: int, torch, device="cuda"):
+    """Seeded m x n FP32 matrix with exact singular values s, built on the
+    device (the Haar construction of the 512 uneven matrices up to 2048^2
+    would take minutes on the host): diag(s) mixed by three Householder
+    reflections on each side, in FP64, then rounded to FP32.  torch is the
+    caller's torch module (this module does not import it)."""
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    A = torch.zeros((m, n), dtype=torch.float64, device=device)
+    r = len(s)
+    A[torch.arange(r), torch.arange(r)] = torch.from_numpy(np.ascontiguousarray(s)).to(device)
+    for _ in range(3):
+        u = torch.randn(m, generator=g, dtype=torch.float64, device=device)
+        u /= u.norm()
+        A -= 2.0 * torch.outer(u, u @ A)
+        v = torch.randn(n, generator=g, dtype=torch.float64, device=device)
+        v /= v.norm()
+        A -= 2.0 * torch.outer(A @ v, v)
+    return A.float().contiguous()
 
 
 def cotangents(m: int, n: int, k: int, seed: int):
