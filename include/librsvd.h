@@ -186,6 +186,46 @@ typedef struct rsvd_plan rsvd_plan_t;
 #define RSVD_PLAN_SAVE 4u    /* keep every intermediate basis and the adjoint workspace for rsvd_plan_backward */
 #define RSVD_PLAN_NO_REFINE 8u /* form B = Q^T A in the sketch precision instead of FP64 (accuracy study) */
 #define RSVD_PLAN_TUNE 16u     /* choose the workgroup tile of every forward product by measurement (below) */
+/* Run the Jacobi SVD as one launch per round of its schedule.  Without this
+ * flag, plans whose rounds have at most 64 block pairs over all problems (small
+ * problems or batches, whose rounds cannot fill the GPU) run the whole Jacobi
+ * phase as one persistent launch whose workgroups take the same block-pair
+ * tasks from a queue and wait only for their own problem's previous round;
+ * both forms compute the same rotations in the same order per problem and
+ * give bit-identical results.  A wait of the persistent launch that exceeds
+ * its bound (a fault, not an expected case) makes every problem of that
+ * execute report RSVD_ERR_HIP in info. */
+#define RSVD_PLAN_ROUND_LAUNCHES 32u
+/* Block-Krylov variant (the faster-converging power scheme named in the
+ * outlook, Sec. V): the small SVD is taken over the whole block Krylov space
+ * span{A Omega, (A A^T) A Omega, ..., (A A^T)^q A Omega} instead of its last
+ * block.  The range finder is unchanged; the q + 1 orthonormal bases of the
+ * stages that multiply by A are placed side by side, the first
+ * L = min((k + p)(q + 1), m, n) columns are orthonormalised (Cholesky QR
+ * twice, Householder on breakdown), and B = Q^T A (L x n), its SVD, the
+ * truncation and U = Q Utilde follow as for the RSVD.  With q = 0 this is the
+ * RSVD.  Truncation, outputs and discarded weight as for the RSVD (w equals
+ * ||A - U S V^T||_F^2).  Not with RSVD_PLAN_FULLSVD or RSVD_PLAN_SAVE; L must
+ * be <= 1024 (RSVD_ERR_INVALID otherwise). */
+#define RSVD_PLAN_BLOCK_KRYLOV 64u
+/* Complex matrices (the paper's simulations run in complex double, Sec. IV):
+ * A, U and VT hold complex double, interleaved (re, im), with leading
+ * dimensions lda, ldu, ldvt counted in complex elements; S holds real
+ * doubles; dtype must be RSVD_F64.  The method is Alg. RSVD (or Alg. TSVD
+ * with RSVD_PLAN_FULLSVD) with Hermitian transposes: Y = A Omega with a
+ * circular complex Gaussian Omega (entry (i, j) = (x + i y) / sqrt(2) with x, y
+ * the Box-Muller pair of the Philox4x32-10 words of counter (i, j, 1, 0) under
+ * the seed's key), W = A^H Q, B = Q^H A, U = Q Utilde, VT = V^H.  Canonical
+ * phases: the entry of largest modulus of each kept column of U (lowest row
+ * on ties) is real and positive, the matching row of VT taking the conjugate
+ * phase.  Truncation and discarded weight as for real problems.  Computed on
+ * the real embedding [[Ar, -Ai], [Ai, Ar]] (2m x 2n, whose singular values are
+ * those of A, twice): the product, orthonormalisation and Jacobi kernels of
+ * the real path at twice the sizes, so the limits are those of the real path
+ * at 2m x 2n, rank 2k and oversampling 2p (min(k + p, m, n) <= 512; full SVD
+ * min(m, n) <= 1024).  Not with RSVD_PLAN_SAVE, RSVD_PLAN_TUNE (the shape
+ * heuristic picks the tiles) or rsvd_plan_postselect. */
+#define RSVD_PLAN_COMPLEX 128u
 
 /* Validates the problems, sizes and allocates the plan's device workspace.
  * Returns RSVD_ERR_INVALID for bad problem descriptions. */

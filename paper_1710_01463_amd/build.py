@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librsvd.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["gemm.hip", "qr.hip", "jacobi.hip", "misc.hip", "adjoint.hip", "select.hip", "librsvd.cpp"]
+SOURCES = ["gemm.hip", "qr.hip", "jacobi.hip", "misc.hip", "adjoint.hip", "select.hip", "complex.hip", "librsvd.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off (they have given silent wrong results on this target)

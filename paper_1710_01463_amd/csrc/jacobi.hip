@@ -199,10 +199,12 @@ __device__ void apply_rotation_resident(const ChunkSeq& cs, double (&res)[NS][JP
 // loaded during the inner solve, so that the global-memory latency is paid
 // about twice per round instead of once per chunk.  RX = 0: chunks are
 // streamed through a one-deep register prefetch (any C and R).
+// Outcome of one block-pair task: the problem had already converged (the
+// previous sweep rotated nothing), or the task ran (rotating or not).
+enum JacOutcome { JAC_CONVERGED = 0, JAC_RAN = 1 };
+
 template <int RX, int RP>
-__global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restrict__ descs,
-                                                           const int* __restrict__ pair_begin, int nprob,
-                                                           int sweep, int round)
+__device__ __forceinline__ int jacobi_pair_task(const JacDesc& d, int slot, int sweep, int round)
 {
     __shared__ double Xs[JR][JCH + 1];
     __shared__ double Hbuf[2][JR][JR + 1];
@@ -210,18 +212,16 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
     __shared__ int rowmap[JR];
     __shared__ int any_rot;
 
-    const int t = blockIdx.x;
-    const int2 wi_ = wg_item(pair_begin, t);
-    const int b = wi_.x;
-    const JacDesc& d = descs[b];
     const int nb = d.nb;
-    if (round >= nb - 1) return;
     GLB int* __restrict__ rot = to_glb(d.rot);
-    if (sweep > 0 && rot[sweep - 1] == 0) return;
+    // (an atomic load: in the persistent kernel another workgroup set the flag
+    // during this launch, and a scalar-cache load could be stale)
+    if (sweep > 0 && __hip_atomic_load((int*)&rot[sweep - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        return JAC_CONVERGED;
     // With an odd number of row blocks, the padding block (nb - 1) takes the
     // fixed position 0 of the round-robin schedule, so that its pair is always
     // slot 0: that slot is not launched (the other blocks sit out once per sweep).
-    const int pi = wi_.y + d.skip0;
+    const int pi = slot + d.skip0;
     int I = rr_block(pi, round, nb);
     int J = rr_block(nb - 1 - pi, round, nb);
     if (d.skip0) {
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
         if (any_rot & 2) atomicAdd((int*)&st[1], 1);
         if (any_rot) rot[sweep] = 1;
     }
-    if (!(any_rot & 2)) return;
+    if (!(any_rot & 2)) return JAC_RAN;
     // resident: the rows of P, in flight during the inner solve
     constexpr int NRP = RP > 0 ? RP : 1;
     double resp[NRP][JPF];
@@ -404,6 +404,119 @@ __global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restr
     } else {
         apply_rotation(seq, pre, rowmap, Ps, Xs);
     }
+    return JAC_RAN;
+}
+
+template <int RX, int RP>
+__global__ __launch_bounds__(JT) void jacobi_round_kernel(const JacDesc* __restrict__ descs,
+                                                           const int* __restrict__ pair_begin, int nprob,
+                                                           int sweep, int round)
+{
+    const int2 wi_ = wg_item(pair_begin, blockIdx.x);
+    const JacDesc& d = descs[wi_.x];
+    if (round >= d.nb - 1) return;
+    (void)jacobi_pair_task<RX, RP>(d, wi_.y, sweep, round);
+}
+
+// All rounds of all sweeps in one launch.  The tasks are the (sweep, round,
+// block pair) items of the round launches above, in the same order: task t
+// is round g = t / total_pairs of the schedule and entry t % total_pairs of
+// the launch's pair map.  Workgroups take tasks from a global counter and
+// wait only for their own problem: a task of local round r (r counts the
+// rounds that problem takes part in) starts once the problem's first r
+// rounds have all finished, which the problem's task counter (stats[2])
+// shows as r * pairs-per-round.  Problems therefore advance independently
+// (no grid-wide step), so one problem's row traffic overlaps another's inner
+// sweeps, and no launch boundary separates the rounds.
+//   - Deadlock freedom: tasks are taken in order and a task depends only on
+//     earlier tasks, which were taken by running workgroups; the earliest
+//     unfinished task always has its dependencies met.  Residency of the
+//     grid is not assumed.
+//   - Memory: a finished task's stores reach every XCD by an agent-scope
+//     release before its counter increment; a waiting task acquires at agent
+//     scope after seeing the count (the L2 of each XCD is written back and
+//     invalidated).  Flags are read with atomic loads, never from the scalar
+//     cache.
+//   - Convergence: the first task of a converged problem sets stats[3]; later
+//     tasks of that problem skip without waiting.
+//   - Every wait is bounded: after spin_limit polls the workgroup sets the
+//     error flag sched[1] and every workgroup leaves at its next poll or
+//     task, so the grid always drains; the finishing step reports the error.
+template <int RX, int RP>
+__global__ __launch_bounds__(JT) void jacobi_persistent_kernel(const JacDesc* __restrict__ descs,
+                                                                const int* __restrict__ pair_map, int total_pairs,
+                                                                int rounds_per_sweep, int max_sweeps,
+                                                                int* __restrict__ sched, int spin_limit)
+{
+    __shared__ int ctl[4];  // task state, problem, slot, schedule round
+    const int tid = threadIdx.x;
+    const int64_t ntasks = (int64_t)max_sweeps * rounds_per_sweep * total_pairs;
+    int* next = sched;
+    int* err = sched + 1;
+    for (;;) {
+        __syncthreads();  // the previous task is done with the shared arrays and ctl
+        if (tid == 0) {
+            // state: 0 no work in this task, 1 run, 2 leave
+            int state = 2, b = 0, slot = 0, g = 0;
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                const int t = __hip_atomic_fetch_add(next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((int64_t)t < ntasks) {
+                    g = t / total_pairs;
+                    const int2 wi = wg_item(pair_map, t % total_pairs);
+                    b = wi.x;
+                    slot = wi.y;
+                    const JacDesc& d = descs[b];
+                    const int sweep = g / rounds_per_sweep, round = g % rounds_per_sweep;
+                    state = 0;
+                    if (round < d.nb - 1) {
+                        int* cnt = d.stats + 2;
+                        int* done = d.stats + 3;
+                        const int np = d.nb / 2 - d.skip0;
+                        const int need = (sweep * (d.nb - 1) + round) * np;
+                        for (int it = 0;; ++it) {
+                            if (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                            if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) {
+                                state = 1;
+                                break;
+                            }
+                            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                                state = 2;
+                                break;
+                            }
+                            if (it >= spin_limit) {
+                                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                state = 2;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(2);
+                        }
+                        // the rows written by the tasks just counted are visible below
+                        if (state == 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    }
+                }
+            }
+            ctl[0] = state;
+            ctl[1] = b;
+            ctl[2] = slot;
+            ctl[3] = g;
+        }
+        __syncthreads();
+        const int state = ctl[0];
+        if (state == 2) break;
+        if (state == 0) continue;
+        const JacDesc& d = descs[ctl[1]];
+        const int g = ctl[3];
+        const int res = jacobi_pair_task<RX, RP>(d, ctl[2], g / rounds_per_sweep, g % rounds_per_sweep);
+        __syncthreads();  // every wave's stores of this task are issued before the release below
+        if (tid == 0) {
+            if (res == JAC_CONVERGED) {
+                __hip_atomic_store(d.stats + 3, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_fetch_add(d.stats + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
 }
 
 int jacobi_resident_variant(int max_x_chunks, int max_p_chunks)
@@ -412,6 +525,40 @@ int jacobi_resident_variant(int max_x_chunks, int max_p_chunks)
     if (max_x_chunks <= 4 && max_p_chunks <= 4) return 2;
     if (max_x_chunks <= 8 && max_p_chunks <= 2) return 3;
     return 0;
+}
+
+template <int RX, int RP>
+static hipError_t persistent_t(const JacDesc* d, const int* pair_map, int total_pairs, int rounds_per_sweep,
+                               int max_sweeps, int* sched, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((jacobi_persistent_kernel<RX, RP>), dim3(grid), dim3(JT), 0, s, d, pair_map, total_pairs,
+                       rounds_per_sweep, max_sweeps, sched, JAC_SPIN_LIMIT);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_persistent(const JacDesc* d, const int* pair_map, int total_pairs, int rounds_per_sweep,
+                                    int max_sweeps, int* sched, int grid, int variant, hipStream_t s)
+{
+    if (total_pairs <= 0 || grid <= 0) return hipSuccess;
+    switch (variant) {
+    case 1: return persistent_t<4, 3>(d, pair_map, total_pairs, rounds_per_sweep, max_sweeps, sched, grid, s);
+    case 2: return persistent_t<4, 4>(d, pair_map, total_pairs, rounds_per_sweep, max_sweeps, sched, grid, s);
+    case 3: return persistent_t<8, 2>(d, pair_map, total_pairs, rounds_per_sweep, max_sweeps, sched, grid, s);
+    default: return persistent_t<0, 0>(d, pair_map, total_pairs, rounds_per_sweep, max_sweeps, sched, grid, s);
+    }
+}
+
+int jacobi_persistent_blocks_per_cu(int variant)
+{
+    int nb = 0;
+    hipError_t e;
+    switch (variant) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, jacobi_persistent_kernel<4, 3>, JT, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, jacobi_persistent_kernel<4, 4>, JT, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, jacobi_persistent_kernel<8, 2>, JT, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, jacobi_persistent_kernel<0, 0>, JT, 0); break;
+    }
+    return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 hipError_t launch_jacobi_round(const JacDesc* d, const int* pair_begin, int nprob, int total_pairs,
@@ -550,6 +697,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinDesc* __restrict__
             w = tail[kk];
         }
         if (info == 0 && d.rot && to_glb(d.rot)[d.max_sweeps - 1] != 0) info = -5;  // sweep cap reached
+        if (d.jac_err && *to_glb(d.jac_err) != 0) info = -3;  // the persistent Jacobi gave up waiting
         kk_s = kk;
         *to_glb(d.w_out) = w;
         *to_glb(d.kkept_out) = kk;

@@ -94,7 +94,8 @@ struct JacDesc {
     double* X;
     double* P;
     int* rot;          // per-sweep "rotated" flags, max_sweeps entries
-    int* stats;        // [0] block pairs whose Gram was formed, [1] rotations applied
+    int* stats;        // [0] block pairs whose Gram was formed, [1] rotations applied,
+                       // [2] tasks finished and [3] converged (persistent launch)
     int64_t ldx, ldp;
     int R, C, nb;
     int skip0;         // 1: block nb - 1 is all padding and its pair is not launched
@@ -111,6 +112,16 @@ constexpr int JAC_CHUNK = 128;
 int jacobi_resident_variant(int max_x_chunks, int max_p_chunks);
 hipError_t launch_jacobi_round(const JacDesc* d, const int* pair_begin, int nprob, int total_pairs,
                                int sweep, int round, int variant, hipStream_t s);
+// Every round of every sweep in one launch of `grid` workgroups that take
+// block-pair tasks from a queue (sched[0], zero before the launch) and wait
+// only on their own problem's earlier rounds (stats[2], stats[3] zero before
+// the launch).  sched[1] (zero before the launch) is set when a wait exceeds
+// JAC_SPIN_LIMIT polls; every workgroup then leaves.
+constexpr int JAC_SPIN_LIMIT = 1 << 22;
+hipError_t launch_jacobi_persistent(const JacDesc* d, const int* pair_map, int total_pairs, int rounds_per_sweep,
+                                    int max_sweeps, int* sched, int grid, int variant, hipStream_t s);
+// Workgroups of the persistent Jacobi kernel that fit on one compute unit.
+int jacobi_persistent_blocks_per_cu(int variant);
 
 // ---------------------------------------------------------------- finishing
 // mode 0: RSVD (X = B rows, w from ||A||^2 - sum), mode 1: full SVD with X = A,
@@ -123,6 +134,7 @@ struct FinDesc {
     int* perm;         // R
     const double* normA2;
     const int* rot;    // Jacobi flags, to detect the sweep cap
+    const int* jac_err; // error flag of the persistent Jacobi launch (may be null)
     void* U;
     void* S;
     void* VT;
@@ -176,13 +188,61 @@ hipError_t launch_stage(const StageDesc* d, const int* chunk_begin, int nprob, i
 hipError_t launch_stage_final(const StageDesc* d, int nprob, hipStream_t s);
 
 // Gaussian test matrix Omega (n x l) of every problem, element type elem.
+// complex_embed: Omega is the real 2n x 2l embedding [[Wr, -Wi], [Wi, Wr]] of
+// the n x l circular complex Gaussian W of the seed (counter (i, j, 1, 0)),
+// n and l being the complex sizes; the item map then covers n l entries.
 struct OmegaDesc {
     void* Om;
     uint64_t seed;
     int n, l;
     int elem;
-    int pad_;
+    int complex_embed;
 };
+
+// Real embedding At = [[Ar, -Ai], [Ai, Ar]] (2m x 2n, FP64, ld ldt) of a complex
+// m x n matrix A stored interleaved (re, im) with leading dimension lda in
+// complex elements.  Item map over ceil(m n / 256) blocks per problem.
+struct CEmbedDesc {
+    const double* A;
+    double* At;
+    int64_t lda, ldt;
+    int m, n;
+};
+hipError_t launch_embed_complex(const CEmbedDesc* d, const int* blk_begin, int nprob, int total_blocks,
+                                hipStream_t s);
+
+// Complex triplets from the real SVD of the embedding (the real singular
+// values come in pairs, sigma_j twice, with the vectors of [u_r; u_i] and of
+// i u): per problem, the 2k leading real triplets of the embedded problem
+// (Ur 2m x 2k, Sr 2k sorted, VTr 2k x 2n) give k complex ones (u = x[:m] +
+// i x[m:], v likewise from the right vector), made orthonormal in the complex
+// inner product against the kept vectors whose values lie within
+// CPLX_MIX_REL sigma_1 (which drops the partner of each kept vector and
+// resolves degenerate clusters).  Then the truncation rule on the complex
+// values, the discarded weight, the canonical phases (largest-modulus entry
+// of u real and positive, the row of V^H taking the conjugate phase) and the
+// interleaved complex outputs U (m x k, ldu), S, VT = V^H (k x n, ldvt).
+constexpr double CPLX_MIX_REL = 1e-4;
+struct CFinDesc {
+    const double* Ur;     // 2m x 2k, ld 2k
+    const double* Sr;     // 2k
+    const double* VTr;    // 2k x 2n, ld 2n
+    const double* normA2; // ||At||_F^2 = 2 ||A||_F^2
+    const double* wr;     // the embedded problem's discarded weight (full SVD: its tail beyond 2k)
+    const int* info_in;   // the embedded problem's status
+    double* U;            // complex m x k (ldu)
+    double* S;            // k
+    double* VT;           // complex k x n (ldvt)
+    double* sig;          // k: the complex singular values
+    double* w_out;
+    int64_t* kkept_out;
+    int* info_out;
+    int64_t ldu, ldvt;
+    int m, n, k;
+    int full;             // 1: full-SVD truncation (w is the tail sum), 0: RSVD (||A||^2 - sum)
+    double delta;
+};
+hipError_t launch_complex_finish(const CFinDesc* d, int nprob, const int* col_map, int col_total, hipStream_t s);
 hipError_t launch_omega(const OmegaDesc* d, const int* blk_begin, int nprob, int total_blocks,
                         hipStream_t s);
 

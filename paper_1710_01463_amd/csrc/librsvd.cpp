@@ -63,6 +63,18 @@ constexpr double JAC_LQ_MIN_RATIO = 4.0;
 // is visited at least once per sweep.  With fewer blocks this costs more extra
 // sweeps than it saves.
 constexpr int JAC_CROSS_MIN_NB = 16;
+// The Jacobi phase runs as one persistent launch when a round has at most
+// JAC_PERSISTENT_MAX_PAIRS block pairs over the whole plan (and the plan at
+// most JAC_PERSISTENT_MAX_TASKS tasks), else round by round.  Measured inside
+// HIP graphs: 1 x 128^2 (3 pairs per round) 1.29 -> 1.24 ms per step and
+// 16 x 1024^2 at l = 80 (48 pairs) 3.27 -> 3.23 ms, where each round is far too
+// small to fill the GPU and the launches dominate; 32 x 500^2 at l = 110 (128
+// pairs) 2.90 -> 2.98 ms and 32 x 512^2 at l = 272 (256 pairs, one per
+// compute unit) 8.93 -> 9.66 ms, where a round fills the GPU and the
+// per-task release/acquire (an L2 write-back and invalidate on the XCD)
+// costs more than the launch boundaries it replaces.
+constexpr int JAC_PERSISTENT_MAX_PAIRS = 64;
+constexpr int64_t JAC_PERSISTENT_MAX_TASKS = 1 << 18;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -95,7 +107,8 @@ struct ProbHost {
         o_flags, o_rot, o_stats, o_info_local;
     std::vector<size_t> o_mstage, o_qstage, o_l1stage, o_l2stage;  // l1/l2: inverse Cholesky factors
     size_t o_lwork, o_dwork;
-    size_t o_bt, o_qb;  // B^T = A^T Q and its orthonormal factor Q_B (n x l, FP64), lq problems only
+    size_t o_bt, o_qb;  // B^T = A^T Q and its orthonormal factor Q_B (n x R, FP64), lq problems only
+    size_t o_kraw, o_kq;  // block-Krylov plans: the power bases side by side (m x R) and their orthonormal basis
     size_t o_sgn;  // k canonical signs written by the sign fix (0 beyond k_kept)
     // reverse pass (RSVD_PLAN_SAVE only)
     size_t o_bw_w[2], o_bw_vbt, o_bw_vts, o_bw_bb, o_bw_ut, o_bw_utb, o_bw_eu, o_bw_ev, o_bw_kp, o_bw_sb;
@@ -153,7 +166,13 @@ struct IdxLaunch {
     int total;
 };
 
+// Private plan flag: the Gaussian test matrix is the real embedding of the
+// complex circular Gaussian (the embedded problems of a complex plan).
+constexpr unsigned PLAN_CPLX_OMEGA = 1u << 30;
+
 }  // namespace
+
+struct ComplexExt;
 
 struct rsvd_plan {
     int nprob = 0;
@@ -161,9 +180,18 @@ struct rsvd_plan {
     rsvd_prec_t prec = RSVD_PREC_F64;
     unsigned flags = 0;
     bool fullsvd = false;
+    bool complex_omega = false;  // embedded complex Gaussian (set on the inner plan of a complex plan)
+    ComplexExt* cx = nullptr;    // RSVD_PLAN_COMPLEX: the embedded real plan and the complex finishing step
     std::vector<ProbHost> probs;
     int max_l = 0, max_nb = 2, max_q = 0;
     int jac_variant = 0;
+    bool krylov = false;          // block-Krylov variant (RSVD_PLAN_BLOCK_KRYLOV)
+    std::vector<IdxLaunch> kcopy; // per stage: copy of the stage's basis into the Krylov block (even stages)
+    GemmLaunch g_kgram1, g_kgram2;
+    IdxLaunch k_qr[2], k_trsm[2];
+    bool jac_persistent = false;  // the Jacobi phase is one persistent launch
+    int jac_grid = 0;             // its workgroups
+    size_t off_sched = 0;         // its task counter and error flag (2 ints, cleared every execute)
     int max_sweeps = 20;
     Elem e_store = E_F64, e_sketch = E_F64, e_y = E_F64;
     bool need_cast = false;
@@ -270,6 +298,7 @@ void layout(rsvd_plan& P)
     P.total_flags = 0;
     for (auto& h : P.probs) {
         const int64_t m = h.m, n = h.n, l = h.l;
+        const int64_t lw = std::max<int64_t>(l, h.R);  // widest basis orthonormalised (the Krylov block)
         h.nchunks = (int)((m + STAGE_ROWS - 1) / STAGE_ROWS);
         h.o_norm = take(sizeof(double));
         h.o_part = take(sizeof(double) * h.nchunks);
@@ -290,8 +319,8 @@ void layout(rsvd_plan& P)
         h.o_l1stage.assign(nst, 0);
         h.o_l2stage.assign(nst, 0);
         size_t shared_m[2], shared_q[2], sl1 = 0, sl2 = 0;
-        h.o_lwork = take(sizeof(double) * l * l);
-        h.o_dwork = take(sizeof(double) * ((l + 15) / 16) * 256);
+        h.o_lwork = take(sizeof(double) * lw * lw);
+        h.o_dwork = take(sizeof(double) * ((lw + 15) / 16) * 256);
         if (!save) {
             shared_m[0] = take((size_t)elem_bytes(P.e_y) * m * l);
             shared_m[1] = take((size_t)elem_bytes(P.e_y) * n * l);
@@ -314,10 +343,12 @@ void layout(rsvd_plan& P)
                 h.o_l2stage[s] = sl2;
             }
         }
-        h.o_g = take(sizeof(double) * l * l);
+        h.o_g = take(sizeof(double) * lw * lw);
         h.o_b = take(sizeof(double) * (size_t)h.R * h.C);
-        h.o_bt = h.lq ? take(sizeof(double) * n * l) : 0;
-        h.o_qb = h.lq ? take(sizeof(double) * n * l) : 0;
+        h.o_bt = h.lq ? take(sizeof(double) * n * h.R) : 0;
+        h.o_qb = h.lq ? take(sizeof(double) * n * h.R) : 0;
+        h.o_kraw = P.krylov ? take(sizeof(double) * m * h.R) : 0;
+        h.o_kq = P.krylov ? take(sizeof(double) * m * h.R) : 0;
         if (save) {
             const int64_t mx = std::max(m, n);
             h.o_bw_w[0] = take(sizeof(double) * mx * l);
@@ -335,14 +366,16 @@ void layout(rsvd_plan& P)
     }
     // flags: per problem (2 q_max + 1) QR flags followed by max_sweeps rot flags
     P.off_flags_base = take(0);
-    // per problem: 2 q_max + 1 stage QR flags, the lq factorisation's, then the sweeps'
-    const int per = (int)(2 * P.max_q + 2) + P.max_sweeps + 2;
+    // per problem: 2 q_max + 1 stage QR flags, the lq factorisation's, the
+    // Krylov block's, then the sweeps' rotation flags and four Jacobi counters
+    const int per = (int)(2 * P.max_q + 3) + P.max_sweeps + 4;
     for (size_t b = 0; b < P.probs.size(); ++b) {
         P.probs[b].o_flags = P.off_flags_base + sizeof(int) * (size_t)per * b;
-        P.probs[b].o_rot = P.probs[b].o_flags + sizeof(int) * (size_t)(2 * P.max_q + 2);
+        P.probs[b].o_rot = P.probs[b].o_flags + sizeof(int) * (size_t)(2 * P.max_q + 3);
         P.probs[b].o_stats = P.probs[b].o_rot + sizeof(int) * (size_t)P.max_sweeps;
     }
-    P.total_flags = per * (int)P.probs.size();
+    P.off_sched = P.off_flags_base + sizeof(int) * (size_t)per * P.probs.size();
+    P.total_flags = per * (int)P.probs.size() + 2;
     off = align_up(P.off_flags_base + sizeof(int) * (size_t)P.total_flags, 256);
     P.ws_bytes = off;
 }
@@ -493,6 +526,41 @@ GemmDesc gd(const void* A, int64_t lda, int transA, const void* X, int64_t ldx, 
     return d;
 }
 
+// Compute units of the current device (queried once per device).
+int compute_units()
+{
+    static std::mutex mu;
+    static std::map<int, int> cus;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cus.find(dev);
+    if (it == cus.end()) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        it = cus.emplace(dev, n).first;
+    }
+    return it->second;
+}
+
+// Resident workgroups per compute unit of the persistent Jacobi kernel variant.
+int persistent_blocks_per_cu(int variant)
+{
+    static std::mutex mu;
+    static std::map<int, int> per;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = per.find(variant);
+    if (it == per.end()) it = per.emplace(variant, jacobi_persistent_blocks_per_cu(variant)).first;
+    return it->second;
+}
+
+// The basis the small SVD is projected on (m x R, FP64): the last stage's
+// basis, or the orthonormalised block-Krylov block.
+const double* final_q(const rsvd_plan& P, const ProbHost& h)
+{
+    return P.krylov ? wsp<double>(P, h.o_kq) : wsp<double>(P, h.o_qstage[2 * h.q]);
+}
+
 // Builds every descriptor table for the given user pointers.
 void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const* S, void* const* VT,
                 double* w, int64_t* kk, int* info)
@@ -552,6 +620,12 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
                 o.elem = P.e_sketch;
                 const int64_t pairs = ((h.n + 1) / 2) * (int64_t)h.l;
                 cnt[b] = (int)((pairs + 255) / 256);
+                if (P.complex_omega) {  // the embedded problem of an m x n complex one: n and l are doubled
+                    o.n = (int)(h.n / 2);
+                    o.l = h.l / 2;
+                    o.complex_embed = 1;
+                    cnt[b] = (int)(((int64_t)o.n * o.l + 255) / 256);
+                }
             }
             P.omega = add_idx(B, d, cnt);
         }
@@ -563,6 +637,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
         P.g_gram2.clear();
         P.qr.clear();
         P.trsm.clear();
+        P.kcopy.clear();
         for (int s = 0; s < nst; ++s) {
             std::vector<GemmDesc> dsk(np), dg1(np), dg2(np);
             std::vector<QrDesc> dq(np), dq2(np);
@@ -626,6 +701,65 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             P.qr.push_back(add_idx(B, dq2, ones));
             P.trsm.push_back(add_idx(B, dq, rowblk));
             P.trsm.push_back(add_idx(B, dq2, rowblk2));
+            // block-Krylov plans: basis j = s / 2 of an even stage goes to columns
+            // j l .. of the Krylov block (its first R = min(l (q + 1), m, n) columns)
+            std::vector<CopyDesc> dc(np);
+            std::vector<int> cc(np, 0);
+            for (int b = 0; b < np; ++b) {
+                const ProbHost& h = P.probs[b];
+                CopyDesc& c = dc[b];
+                memset(&c, 0, sizeof(c));
+                const int c0 = (s / 2) * h.l, ncols = std::min(h.l, h.R - c0);
+                if (!P.krylov || s % 2 == 1 || s > 2 * h.q || ncols <= 0) continue;
+                c.A = wsp<double>(P, h.o_qstage[s]);
+                c.X = wsp<double>(P, h.o_kraw) + c0;
+                c.lda = h.l;
+                c.ldx = h.R;
+                c.m = (int)h.m;
+                c.n = ncols;
+                c.a_elem = E_F64;
+                c.transpose = 0;
+                cc[b] = (int)(((h.m + 63) / 64) * ((ncols + 63) / 64));
+            }
+            P.kcopy.push_back(add_idx(B, dc, cc));
+        }
+        // block-Krylov plans: the Krylov block K = Q_K R_K by Cholesky QR twice
+        // (Householder on breakdown); Q_K is the basis of the projection
+        if (P.krylov) {
+            std::vector<GemmDesc> dg1(np), dg2(np);
+            std::vector<QrDesc> dq(np), dq2(np);
+            std::vector<int> rowblk(np), ones(np, 1);
+            for (int b = 0; b < np; ++b) {
+                const ProbHost& h = P.probs[b];
+                const int L = h.R;
+                double* K = wsp<double>(P, h.o_kraw);
+                double* Qk = wsp<double>(P, h.o_kq);
+                double* G = wsp<double>(P, h.o_g);
+                int* flag = wsp<int>(P, h.o_flags) + 2 * P.max_q + 2;
+                dg1[b] = gd(K, L, 1, K, L, 0, G, L, L, L, (int)h.m, flag);
+                dg1[b].lower = 1;
+                dg2[b] = gd(Qk, L, 1, Qk, L, 0, G, L, L, L, (int)h.m, flag);
+                dg2[b].lower = 1;
+                QrDesc& q = dq[b];
+                memset(&q, 0, sizeof(q));
+                q.Min = K;
+                q.Qout = Qk;
+                q.G = G;
+                q.L = wsp<double>(P, h.o_lwork);
+                q.D = wsp<double>(P, h.o_dwork);
+                q.flag = flag;
+                q.rows = (int)h.m;
+                q.l = L;
+                q.min_elem = E_F64;
+                dq2[b] = q;
+                rowblk[b] = (int)((h.m + 15) / 16);
+            }
+            P.g_kgram1 = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, dg1);
+            P.g_kgram2 = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, dg2);
+            P.k_qr[0] = add_idx(B, dq, ones);
+            P.k_qr[1] = add_idx(B, dq2, ones);
+            P.k_trsm[0] = add_idx(B, dq, rowblk);
+            P.k_trsm[1] = add_idx(B, dq2, rowblk);
         }
         // lq problems: B^T = A^T Q (FP64 from the stored A) and its Cholesky QR
         // (two passes, Householder on breakdown), B^T = Q_B R
@@ -638,7 +772,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             const GemmDesc none = gd(nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0, 0, 0, one);
             for (int b = 0; b < np; ++b) {
                 const ProbHost& h = P.probs[b];
-                const int l = h.l;
+                const int l = h.R;  // width of the final basis
                 memset(&dq[b], 0, sizeof(QrDesc));
                 dq[b].flag = const_cast<int*>(one);
                 dq[b].l = l;
@@ -649,7 +783,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
                 double* Qb = wsp<double>(P, h.o_qb);
                 double* G = wsp<double>(P, h.o_g);
                 int* flag = wsp<int>(P, h.o_flags) + 2 * P.max_q + 1;
-                dbt[b] = gd(A[b], h.lda, 1, wsp<double>(P, h.o_qstage[2 * h.q]), l, 0, Bt, l, (int)h.n, l, (int)h.m);
+                dbt[b] = gd(A[b], h.lda, 1, final_q(P, h), l, 0, Bt, l, (int)h.n, l, (int)h.m);
                 dg1[b] = gd(Bt, l, 1, Bt, l, 0, G, l, l, l, (int)h.n, flag);
                 dg1[b].lower = 1;
                 QrDesc& q = dq[b];
@@ -682,8 +816,8 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             for (int b = 0; b < np; ++b) {
                 const ProbHost& h = P.probs[b];
                 if (h.lq)
-                    dx[b] = gd(wsp<double>(P, h.o_bt), h.l, 1, wsp<double>(P, h.o_qb), h.l, 0, wsp<double>(P, h.o_b),
-                               h.l, h.l, h.l, (int)h.n);
+                    dx[b] = gd(wsp<double>(P, h.o_bt), h.R, 1, wsp<double>(P, h.o_qb), h.R, 0, wsp<double>(P, h.o_b),
+                               h.R, h.R, h.R, (int)h.n);
             }
             P.g_lqx = tgemm(GK_F64, E_F64, E_F64, E_F64, dx);
         }
@@ -692,11 +826,11 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             std::vector<GemmDesc> d(np);
             for (int b = 0; b < np; ++b) {
                 const ProbHost& h = P.probs[b];
-                const double* Qf = wsp<double>(P, h.o_qstage[2 * h.q]);
+                const double* Qf = final_q(P, h);
                 if (h.lq)
                     d[b] = gd(nullptr, 0, 0, nullptr, 0, 0, nullptr, 0, 0, 0, 0, one);
                 else
-                    d[b] = gd(Qf, h.l, 1, A[b], h.lda, 0, wsp<double>(P, h.o_b), h.n, h.l, (int)h.n, (int)h.m);
+                    d[b] = gd(Qf, h.R, 1, A[b], h.lda, 0, wsp<double>(P, h.o_b), h.n, h.R, (int)h.n, (int)h.m);
             }
             if ((P.flags & RSVD_PLAN_NO_REFINE) && P.prec != RSVD_PREC_F64) {
                 // B = Q^T A with the sketch arithmetic (operands rounded on load)
@@ -773,6 +907,13 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             mp = std::max(mp, (P.probs[b].R + JAC_CHUNK - 1) / JAC_CHUNK);
         }
         P.jac_variant = jacobi_resident_variant(mx, mp);
+        const int64_t ntasks = (int64_t)P.max_sweeps * (P.max_nb - 1) * P.jac.total;
+        P.jac_persistent = !(P.flags & RSVD_PLAN_ROUND_LAUNCHES) && P.jac.total <= JAC_PERSISTENT_MAX_PAIRS &&
+                           ntasks <= JAC_PERSISTENT_MAX_TASKS;
+        if (P.jac_persistent) {
+            const int64_t res = (int64_t)persistent_blocks_per_cu(P.jac_variant) * compute_units();
+            P.jac_grid = (int)std::max<int64_t>(1, std::min(ntasks, res));
+        }
     }
     // finish + sign fix
     {
@@ -807,6 +948,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             f.mode = h.mode;
             f.max_sweeps = P.max_sweeps;
             f.delta = h.delta;
+            f.jac_err = P.jac_persistent ? wsp<int>(P, P.off_sched) + 1 : nullptr;
             rows4[b] = (h.R + 3) / 4;
             vt4[b] = (int)((h.k + 3) / 4);
             utiles[b] = h.mode == 0 ? 0 : (int)(((h.k + 63) / 64) * ((h.m + 63) / 64));
@@ -819,8 +961,8 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             const ProbHost& h = P.probs[b];
             if (!h.lq) continue;
             dfin[b].VT = wsp<double>(P, h.o_g);
-            dfin[b].ldvt = h.l;
-            dfin[b].n = h.l;
+            dfin[b].ldvt = h.R;
+            dfin[b].n = h.R;
         }
         P.finish = add_idx(B, dfin, ones);
         P.fin_norm = add_idx(B, dfin, rows4);
@@ -833,8 +975,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
         std::vector<GemmDesc> d(np);
         for (int b = 0; b < np; ++b) {
             const ProbHost& h = P.probs[b];
-            const double* Qf = wsp<double>(P, h.o_qstage[2 * h.q]);
-            d[b] = gd(Qf, h.l, 0, wsp<double>(P, h.o_p), h.l, 1, U[b], h.ldu, (int)h.m, (int)h.k, h.l,
+            d[b] = gd(final_q(P, h), h.R, 0, wsp<double>(P, h.o_p), h.R, 1, U[b], h.ldu, (int)h.m, (int)h.k, h.R,
                       nullptr, wsp<int>(P, h.o_perm));
         }
         P.g_u = add_gemm(B, GK_F64, E_F64, E_F64, P.dt == RSVD_F64 ? E_F64 : E_F32, d);
@@ -844,8 +985,8 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             for (int b = 0; b < np; ++b) {
                 const ProbHost& h = P.probs[b];
                 if (h.lq)
-                    dv[b] = gd(wsp<double>(P, h.o_g), h.l, 0, wsp<double>(P, h.o_qb), h.l, 1, VT[b], h.ldvt, (int)h.k,
-                               (int)h.n, h.l);
+                    dv[b] = gd(wsp<double>(P, h.o_g), h.R, 0, wsp<double>(P, h.o_qb), h.R, 1, VT[b], h.ldvt, (int)h.k,
+                               (int)h.n, h.R);
             }
             // W holds the finishing step's output type (it is written like V^T)
             const Elem eo = P.dt == RSVD_F64 ? E_F64 : E_F32;
@@ -1062,6 +1203,23 @@ int enqueue(rsvd_plan& P, hipStream_t s)
             }
             // Householder for the problems whose Cholesky QR broke down
             PLAUNCH(RSVD_PHASE_HOUSEHOLDER, 0.0, launch_householder(dp<QrDesc>(P, q1.off_desc), np, s));
+            if (P.krylov && P.kcopy[st].total > 0)
+                PLAUNCH(RSVD_PHASE_OTHER, 0.0,
+                        launch_copy_f64(dp<CopyDesc>(P, P.kcopy[st].off_desc), dp<int>(P, P.kcopy[st].off_begin), np,
+                                        P.kcopy[st].total, s));
+        }
+        if (P.krylov) {
+            if ((rc = gemm(P, P.g_kgram1, s, RSVD_PHASE_GRAM)) != RSVD_OK) return rc;
+            PLAUNCH(RSVD_PHASE_CHOL, 0.0, launch_chol(dp<QrDesc>(P, P.k_qr[0].off_desc), np, P.max_l, s));
+            PLAUNCH(RSVD_PHASE_TRSM, 0.0,
+                    launch_trsm(dp<QrDesc>(P, P.k_trsm[0].off_desc), dp<int>(P, P.k_trsm[0].off_begin), np,
+                                P.k_trsm[0].total, 1, E_F64, P.max_l, s));
+            if ((rc = gemm(P, P.g_kgram2, s, RSVD_PHASE_GRAM)) != RSVD_OK) return rc;
+            PLAUNCH(RSVD_PHASE_CHOL, 0.0, launch_chol(dp<QrDesc>(P, P.k_qr[1].off_desc), np, P.max_l, s));
+            PLAUNCH(RSVD_PHASE_TRSM, 0.0,
+                    launch_trsm(dp<QrDesc>(P, P.k_trsm[1].off_desc), dp<int>(P, P.k_trsm[1].off_begin), np,
+                                P.k_trsm[1].total, 0, E_F64, P.max_l, s));
+            PLAUNCH(RSVD_PHASE_HOUSEHOLDER, 0.0, launch_householder(dp<QrDesc>(P, P.k_qr[0].off_desc), np, s));
         }
         if (P.any_lq) {
             if ((rc = gemm(P, P.g_lqbt, s, RSVD_PHASE_PROJECT)) != RSVD_OK) return rc;
@@ -1085,11 +1243,18 @@ int enqueue(rsvd_plan& P, hipStream_t s)
     }
     PLAUNCH(RSVD_PHASE_OTHER, 0.0,
             launch_eye(dp<EyeDesc>(P, P.eye.off_desc), dp<int>(P, P.eye.off_begin), np, P.eye.total, s));
-    for (int sw = 0; sw < P.max_sweeps; ++sw)
-        for (int r = 0; r < P.max_nb - 1; ++r)
-            PLAUNCH(RSVD_PHASE_JACOBI, 0.0,
-                    launch_jacobi_round(dp<JacDesc>(P, P.jac.off_desc), dp<int>(P, P.jac.off_begin), np, P.jac.total,
-                                        sw, r, P.jac_variant, s));
+    if (P.jac_persistent) {
+        PLAUNCH(RSVD_PHASE_JACOBI, 0.0,
+                launch_jacobi_persistent(dp<JacDesc>(P, P.jac.off_desc), dp<int>(P, P.jac.off_begin), P.jac.total,
+                                         P.max_nb - 1, P.max_sweeps, wsp<int>(P, P.off_sched), P.jac_grid,
+                                         P.jac_variant, s));
+    } else {
+        for (int sw = 0; sw < P.max_sweeps; ++sw)
+            for (int r = 0; r < P.max_nb - 1; ++r)
+                PLAUNCH(RSVD_PHASE_JACOBI, 0.0,
+                        launch_jacobi_round(dp<JacDesc>(P, P.jac.off_desc), dp<int>(P, P.jac.off_begin), np,
+                                            P.jac.total, sw, r, P.jac_variant, s));
+    }
     PLAUNCH(RSVD_PHASE_FINISH, 0.0,
             launch_finish(dp<FinDesc>(P, P.finish.off_desc), np, dp<int>(P, P.fin_norm.off_begin), P.fin_norm.total,
                           dp<int>(P, P.fin_vt.off_begin), P.fin_vt.total, dp<int>(P, P.fin_u.off_begin), P.fin_u.total,
@@ -1358,6 +1523,8 @@ int plan_backward(rsvd_plan* P, const void* const* dU, const void* const* dS, co
     return enqueue_backward(*P, stream);
 }
 
+void complex_free(ComplexExt* X);
+
 void plan_free(rsvd_plan* P)
 {
     if (!P) return;
@@ -1373,6 +1540,7 @@ void plan_free(rsvd_plan* P)
     if (P->bw.upload_done) (void)hipEventDestroy(P->bw.upload_done);
     if (P->bw.dblob) (void)hipFree(P->bw.dblob);
     if (P->bw.hpinned) (void)hipHostFree(P->bw.hpinned);
+    complex_free(P->cx);
     delete P;
 }
 
@@ -1400,10 +1568,22 @@ int plan_setup(rsvd_plan* P, const rsvd_problem_t* probs, int64_t batch, rsvd_dt
     if (prec != RSVD_PREC_F64 && prec != RSVD_PREC_F32 && prec != RSVD_PREC_BF16)
         return fail(RSVD_ERR_INVALID, "unknown precision");
     const bool fullsvd = (flags & RSVD_PLAN_FULLSVD) != 0;
+    const bool krylov = (flags & RSVD_PLAN_BLOCK_KRYLOV) != 0;
+    if (krylov && (fullsvd || (flags & RSVD_PLAN_SAVE)))
+        return fail(RSVD_ERR_INVALID, "block-Krylov plans are RSVD plans without a saved forward");
     for (int64_t b = 0; b < batch; ++b) {
         int rc = validate_problem(probs[b], fullsvd);
         if (rc != RSVD_OK) return fail(rc, "problem " + std::to_string(b) + ": " + g_err);
+        if (krylov) {
+            const int64_t mn = std::min(probs[b].m, probs[b].n);
+            const int64_t l = std::min(std::min(probs[b].k, mn) + probs[b].p, mn);
+            if (std::min(l * (probs[b].q + 1), mn) > 1024)
+                return fail(RSVD_ERR_INVALID, "problem " + std::to_string(b) +
+                                                  ": the block-Krylov width min((k + p)(q + 1), m, n) must be <= 1024");
+        }
     }
+    P->krylov = krylov;
+    P->complex_omega = (flags & PLAN_CPLX_OMEGA) != 0;
     P->nprob = (int)batch;
     P->dt = dt;
     P->prec = fullsvd ? RSVD_PREC_F64 : prec;
@@ -1437,17 +1617,18 @@ int plan_setup(rsvd_plan* P, const rsvd_problem_t* probs, int64_t batch, rsvd_dt
             h.lq = false;
         } else {
             h.l = (int)std::min(h.k + p.p, mn);
-            h.R = h.l;
+            // rows of B: the sketch width, or the block-Krylov width min(l (q + 1), m, n)
+            h.R = krylov ? (int)std::min<int64_t>((int64_t)h.l * (h.q + 1), mn) : h.l;
             h.lq = !(flags & RSVD_PLAN_SAVE) &&
-                   !((flags & RSVD_PLAN_NO_REFINE) && prec != RSVD_PREC_F64) && (double)p.n >= JAC_LQ_MIN_RATIO * h.l;
-            h.C = h.lq ? h.l : (int)p.n;
+                   !((flags & RSVD_PLAN_NO_REFINE) && prec != RSVD_PREC_F64) && (double)p.n >= JAC_LQ_MIN_RATIO * h.R;
+            h.C = h.lq ? h.R : (int)p.n;
             h.mode = 0;
         }
         int nbk = (h.R + JAC_B - 1) / JAC_B;
         if (nbk % 2) ++nbk;
         if (nbk < 2) nbk = 2;
         h.nb = nbk;
-        P->max_l = std::max(P->max_l, h.l);
+        P->max_l = std::max(P->max_l, std::max(h.l, h.R));
         P->max_nb = std::max(P->max_nb, h.nb);
         P->max_q = std::max<int>(P->max_q, (int)h.q);
     }
@@ -1492,6 +1673,36 @@ int plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsv
     return RSVD_OK;
 }
 
+// Builds and uploads the descriptor tables for these pointers unless the
+// last upload was for the same ones.
+int ensure_blob(rsvd_plan* P, const void* const* A, void* const* U, void* const* S, void* const* VT, double* w,
+                int64_t* kk, int* info, hipStream_t stream)
+{
+    bool same = P->blob_valid && P->lastW == w && P->lastK == kk && P->lastInfo == info;
+    if (same) {
+        for (int b = 0; b < P->nprob && same; ++b)
+            same = P->lastA[b] == A[b] && P->lastU[b] == U[b] && P->lastS[b] == S[b] && P->lastVT[b] == VT[b];
+    }
+    if (same) return RSVD_OK;
+    if (P->upload_pending) HIPCHK(hipEventSynchronize(P->upload_done));
+    build_blob(*P, A, U, S, VT, w, kk, info);
+    if (P->hb.bytes.size() != P->blob_bytes) return fail(RSVD_ERR_HIP, "descriptor layout changed");
+    memcpy(P->hblob_pinned, P->hb.bytes.data(), P->blob_bytes);
+    HIPCHK(hipMemcpyAsync(P->dblob, P->hblob_pinned, P->blob_bytes, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipEventRecord(P->upload_done, stream));
+    P->upload_pending = true;
+    P->lastA.assign(A, A + P->nprob);
+    P->lastU.assign(U, U + P->nprob);
+    P->lastS.assign(S, S + P->nprob);
+    P->lastVT.assign(VT, VT + P->nprob);
+    P->lastW = w;
+    P->lastK = kk;
+    P->lastInfo = info;
+    P->blob_valid = true;
+    ++P->fwd_gen;
+    return RSVD_OK;
+}
+
 int plan_execute(rsvd_plan* P, const void* const* A, void* const* U, void* const* S, void* const* VT, double* w,
                  int64_t* kk, int* info, hipStream_t stream)
 {
@@ -1499,29 +1710,8 @@ int plan_execute(rsvd_plan* P, const void* const* A, void* const* U, void* const
     if (!A || !U || !S || !VT || !w || !kk) return fail(RSVD_ERR_INVALID, "null output or input array");
     for (int b = 0; b < P->nprob; ++b)
         if (!A[b] || !U[b] || !S[b] || !VT[b]) return fail(RSVD_ERR_INVALID, "null matrix pointer in batch");
-    bool same = P->blob_valid && P->lastW == w && P->lastK == kk && P->lastInfo == info;
-    if (same) {
-        for (int b = 0; b < P->nprob && same; ++b)
-            same = P->lastA[b] == A[b] && P->lastU[b] == U[b] && P->lastS[b] == S[b] && P->lastVT[b] == VT[b];
-    }
-    if (!same) {
-        if (P->upload_pending) HIPCHK(hipEventSynchronize(P->upload_done));
-        build_blob(*P, A, U, S, VT, w, kk, info);
-        if (P->hb.bytes.size() != P->blob_bytes) return fail(RSVD_ERR_HIP, "descriptor layout changed");
-        memcpy(P->hblob_pinned, P->hb.bytes.data(), P->blob_bytes);
-        HIPCHK(hipMemcpyAsync(P->dblob, P->hblob_pinned, P->blob_bytes, hipMemcpyHostToDevice, stream));
-        HIPCHK(hipEventRecord(P->upload_done, stream));
-        P->upload_pending = true;
-        P->lastA.assign(A, A + P->nprob);
-        P->lastU.assign(U, U + P->nprob);
-        P->lastS.assign(S, S + P->nprob);
-        P->lastVT.assign(VT, VT + P->nprob);
-        P->lastW = w;
-        P->lastK = kk;
-        P->lastInfo = info;
-        P->blob_valid = true;
-        ++P->fwd_gen;
-    }
+    int rc0 = ensure_blob(P, A, U, S, VT, w, kk, info, stream);
+    if (rc0 != RSVD_OK) return rc0;
     P->fwd_saved = false;
     if ((P->flags & RSVD_PLAN_TUNE) && !P->tuned && !P->fullsvd) {
         // one eager execute that times the candidate tiles of every tunable
@@ -1566,6 +1756,279 @@ int plan_execute(rsvd_plan* P, const void* const* A, void* const* U, void* const
     }
     P->fwd_saved = (P->flags & RSVD_PLAN_SAVE) != 0 && !P->fullsvd;
     return RSVD_OK;
+}
+
+// ---------------------------------------------------------------- complex plans
+}  // namespace
+
+// RSVD_PLAN_COMPLEX: the problems are complex (A, U, VT interleaved complex
+// double, S real).  Each runs as the real plan of its embedding
+// At = [[Ar, -Ai], [Ai, Ar]] (2m x 2n, rank 2k, oversampling 2p, the same
+// q and seed, the embedded complex Gaussian as test matrix, no truncation);
+// the complex finishing step then picks one real triplet per pair, applies
+// the truncation rule to the complex values and writes the complex outputs.
+struct ComplexExt {
+    rsvd_plan* inner = nullptr;
+    char* ws = nullptr;  // per problem: At, the inner U, S, VT, sig; then the inner w, k_kept, info arrays
+    size_t ws_bytes = 0;
+    struct Prob {
+        int64_t m, n, lda, k, ldu, ldvt;
+        double delta;
+        size_t o_at, o_u, o_s, o_vt, o_sig;
+    };
+    std::vector<Prob> probs;
+    size_t o_w = 0, o_kk = 0, o_info = 0, o_info_local = 0;
+    // descriptors of the embedding and finishing launches
+    Blob hb;
+    char* dblob = nullptr;
+    char* hpinned = nullptr;
+    size_t blob_bytes = 0;
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
+    IdxLaunch embed, cols;
+    size_t off_cfin = 0;
+    std::vector<const void*> lastA;
+    std::vector<void*> lastU, lastS, lastVT;
+    double* lastW = nullptr;
+    int64_t* lastK = nullptr;
+    int* lastInfo = nullptr;
+    bool blob_valid = false;
+};
+
+namespace {
+
+void complex_free(ComplexExt* X)
+{
+    if (!X) return;
+    if (X->inner) plan_free(X->inner);
+    if (X->ws) (void)hipFree(X->ws);
+    if (X->dblob) (void)hipFree(X->dblob);
+    if (X->hpinned) (void)hipHostFree(X->hpinned);
+    if (X->upload_done) (void)hipEventDestroy(X->upload_done);
+    delete X;
+}
+
+void complex_build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const* S, void* const* VT,
+                        double* w, int64_t* kk, int* info)
+{
+    ComplexExt& X = *P.cx;
+    const int np = P.nprob;
+    Blob B;
+    std::vector<CEmbedDesc> de(np);
+    std::vector<CFinDesc> df(np);
+    std::vector<int> ce(np), cc(np);
+    for (int b = 0; b < np; ++b) {
+        const ComplexExt::Prob& h = X.probs[b];
+        CEmbedDesc& e = de[b];
+        memset(&e, 0, sizeof(e));
+        e.A = (const double*)A[b];
+        e.At = (double*)(X.ws + h.o_at);
+        e.lda = h.lda;
+        e.ldt = 2 * h.n;
+        e.m = (int)h.m;
+        e.n = (int)h.n;
+        ce[b] = (int)((h.m * h.n + 255) / 256);
+        CFinDesc& f = df[b];
+        memset(&f, 0, sizeof(f));
+        f.Ur = (const double*)(X.ws + h.o_u);
+        f.Sr = (const double*)(X.ws + h.o_s);
+        f.VTr = (const double*)(X.ws + h.o_vt);
+        f.normA2 = (const double*)(X.inner->ws + X.inner->probs[b].o_norm);
+        f.wr = (const double*)(X.ws + X.o_w) + b;
+        f.info_in = (const int*)(X.ws + X.o_info) + b;
+        f.U = (double*)U[b];
+        f.S = (double*)S[b];
+        f.VT = (double*)VT[b];
+        f.sig = (double*)(X.ws + h.o_sig);
+        f.w_out = w + b;
+        f.kkept_out = kk + b;
+        f.info_out = info ? info + b : (int*)(X.ws + X.o_info_local) + b;
+        f.ldu = h.ldu;
+        f.ldvt = h.ldvt;
+        f.m = (int)h.m;
+        f.n = (int)h.n;
+        f.k = (int)h.k;
+        f.full = P.fullsvd ? 1 : 0;
+        f.delta = h.delta;
+        cc[b] = (int)h.k;
+    }
+    X.embed = add_idx(B, de, ce);
+    X.cols = add_idx(B, df, cc);
+    X.off_cfin = X.cols.off_desc;
+    X.hb = std::move(B);
+}
+
+int complex_plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt, rsvd_prec_t prec,
+                        unsigned flags, rsvd_plan** out)
+{
+    if (!probs || batch < 1 || batch > (1 << 20)) return fail(RSVD_ERR_INVALID, "batch must be in [1, 2^20]");
+    if (dt != RSVD_F64) return fail(RSVD_ERR_INVALID, "complex plans hold complex double (dtype RSVD_F64)");
+    if (flags & RSVD_PLAN_SAVE) return fail(RSVD_ERR_INVALID, "complex plans have no adjoint (RSVD_PLAN_SAVE)");
+    const bool full = (flags & RSVD_PLAN_FULLSVD) != 0;
+    std::vector<rsvd_problem_t> in(batch);
+    for (int64_t b = 0; b < batch; ++b) {
+        const rsvd_problem_t& p = probs[b];
+        int rc = validate_problem(p, full);
+        if (rc != RSVD_OK) return fail(rc, "problem " + std::to_string(b) + ": " + g_err);
+        const int64_t kk = std::min(p.k, std::min(p.m, p.n));
+        rsvd_problem_t& q = in[b];
+        q.m = 2 * p.m;
+        q.n = 2 * p.n;
+        q.lda = 2 * p.n;
+        q.k = 2 * kk;
+        q.p = 2 * p.p;
+        q.q = p.q;
+        q.seed = p.seed;
+        q.delta_trunc = 0.0;  // the complex finishing step applies the cut
+        q.ldu = 0;
+        q.ldvt = 0;
+    }
+    rsvd_plan* P = new rsvd_plan();
+    P->nprob = (int)batch;
+    P->dt = dt;
+    P->prec = full ? RSVD_PREC_F64 : prec;
+    P->flags = flags;
+    P->fullsvd = full;
+    P->cx = new ComplexExt();
+    ComplexExt& X = *P->cx;
+    const unsigned inner_flags =
+        (flags & (RSVD_PLAN_FULLSVD | RSVD_PLAN_NO_REFINE | RSVD_PLAN_ROUND_LAUNCHES | RSVD_PLAN_BLOCK_KRYLOV)) |
+        (full ? 0u : PLAN_CPLX_OMEGA);
+    int rc = plan_create(in.data(), batch, RSVD_F64, prec, inner_flags, &X.inner);
+    if (rc != RSVD_OK) {
+        plan_free(P);
+        return rc;
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1), 256);
+        return o;
+    };
+    X.probs.resize(batch);
+    for (int64_t b = 0; b < batch; ++b) {
+        const rsvd_problem_t& p = probs[b];
+        ComplexExt::Prob& h = X.probs[b];
+        h.m = p.m;
+        h.n = p.n;
+        h.lda = p.lda;
+        h.k = std::min(p.k, std::min(p.m, p.n));
+        h.ldu = p.ldu ? p.ldu : h.k;
+        h.ldvt = p.ldvt ? p.ldvt : p.n;
+        h.delta = p.delta_trunc;
+        h.o_at = take(sizeof(double) * 4 * h.m * h.n);
+        h.o_u = take(sizeof(double) * 2 * h.m * 2 * h.k);
+        h.o_s = take(sizeof(double) * 2 * h.k);
+        h.o_vt = take(sizeof(double) * 2 * h.k * 2 * h.n);
+        h.o_sig = take(sizeof(double) * h.k);
+    }
+    X.o_w = take(sizeof(double) * batch);
+    X.o_kk = take(sizeof(int64_t) * batch);
+    X.o_info = take(sizeof(int) * batch);
+    X.o_info_local = take(sizeof(int) * batch);
+    X.ws_bytes = off;
+    hipError_t e = hipMalloc(&X.ws, X.ws_bytes);
+    if (e != hipSuccess) {
+        plan_free(P);
+        return fail(RSVD_ERR_ALLOC, std::string("complex workspace hipMalloc: ") + hipGetErrorString(e));
+    }
+    {
+        std::vector<const void*> A(batch, (const void*)X.ws);
+        std::vector<void*> O(batch, (void*)X.ws);
+        complex_build_blob(*P, A.data(), O.data(), O.data(), O.data(), (double*)X.ws, (int64_t*)X.ws, nullptr);
+        X.blob_bytes = X.hb.bytes.size();
+    }
+    e = hipMalloc(&X.dblob, std::max<size_t>(X.blob_bytes, 64));
+    if (e == hipSuccess) e = hipHostMalloc(&X.hpinned, std::max<size_t>(X.blob_bytes, 64), 0);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&X.upload_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        plan_free(P);
+        return fail(RSVD_ERR_ALLOC, std::string("complex plan allocation: ") + hipGetErrorString(e));
+    }
+    *out = P;
+    return RSVD_OK;
+}
+
+// The embedding, the embedded plan's launches and the complex finishing step.
+int complex_enqueue(rsvd_plan& P, hipStream_t s)
+{
+    ComplexExt& X = *P.cx;
+    const int np = P.nprob;
+    const char* db = X.dblob;
+    PLAUNCH(RSVD_PHASE_STAGE, 0.0,
+            launch_embed_complex((const CEmbedDesc*)(db + X.embed.off_desc), (const int*)(db + X.embed.off_begin), np,
+                                 X.embed.total, s));
+    X.inner->prof = P.prof;
+    int rc = enqueue(*X.inner, s);
+    X.inner->prof = nullptr;
+    if (rc != RSVD_OK) return rc;
+    PLAUNCH(RSVD_PHASE_FINISH, 0.0,
+            launch_complex_finish((const CFinDesc*)(db + X.off_cfin), np, (const int*)(db + X.cols.off_begin),
+                                  X.cols.total, s));
+    return RSVD_OK;
+}
+
+int complex_execute(rsvd_plan* P, const void* const* A, void* const* U, void* const* S, void* const* VT, double* w,
+                    int64_t* kk, int* info, hipStream_t stream, bool eager)
+{
+    ComplexExt& X = *P->cx;
+    const int np = P->nprob;
+    if (!A || !U || !S || !VT || !w || !kk) return fail(RSVD_ERR_INVALID, "null output or input array");
+    for (int b = 0; b < np; ++b)
+        if (!A[b] || !U[b] || !S[b] || !VT[b]) return fail(RSVD_ERR_INVALID, "null matrix pointer in batch");
+    // the embedded plan's pointers are internal and never change
+    {
+        std::vector<const void*> Ai(np);
+        std::vector<void*> Ui(np), Si(np), Vi(np);
+        for (int b = 0; b < np; ++b) {
+            Ai[b] = X.ws + X.probs[b].o_at;
+            Ui[b] = X.ws + X.probs[b].o_u;
+            Si[b] = X.ws + X.probs[b].o_s;
+            Vi[b] = X.ws + X.probs[b].o_vt;
+        }
+        int rc = ensure_blob(X.inner, Ai.data(), Ui.data(), Si.data(), Vi.data(), (double*)(X.ws + X.o_w),
+                             (int64_t*)(X.ws + X.o_kk), (int*)(X.ws + X.o_info), stream);
+        if (rc != RSVD_OK) return rc;
+    }
+    bool same = X.blob_valid && X.lastW == w && X.lastK == kk && X.lastInfo == info;
+    for (int b = 0; b < np && same; ++b)
+        same = X.lastA[b] == A[b] && X.lastU[b] == U[b] && X.lastS[b] == S[b] && X.lastVT[b] == VT[b];
+    if (!same) {
+        if (X.upload_pending) HIPCHK(hipEventSynchronize(X.upload_done));
+        complex_build_blob(*P, A, U, S, VT, w, kk, info);
+        if (X.hb.bytes.size() != X.blob_bytes) return fail(RSVD_ERR_HIP, "descriptor layout changed");
+        memcpy(X.hpinned, X.hb.bytes.data(), X.blob_bytes);
+        HIPCHK(hipMemcpyAsync(X.dblob, X.hpinned, X.blob_bytes, hipMemcpyHostToDevice, stream));
+        HIPCHK(hipEventRecord(X.upload_done, stream));
+        X.upload_pending = true;
+        X.lastA.assign(A, A + np);
+        X.lastU.assign(U, U + np);
+        X.lastS.assign(S, S + np);
+        X.lastVT.assign(VT, VT + np);
+        X.lastW = w;
+        X.lastK = kk;
+        X.lastInfo = info;
+        X.blob_valid = true;
+    }
+    if ((P->flags & RSVD_PLAN_GRAPH) && !eager) {
+        if (!P->gexec) {
+            HIPCHK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+            int rc = complex_enqueue(*P, P->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
+            if (rc != RSVD_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return fail(RSVD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+            P->graph = g;
+            HIPCHK(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+        }
+        HIPCHK(hipGraphLaunch(P->gexec, stream));
+        return RSVD_OK;
+    }
+    return eager ? RSVD_OK : complex_enqueue(*P, stream);
 }
 
 // ---------------------------------------------------------------- one-shot cache
@@ -1827,6 +2290,12 @@ int rsvd_plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t dt
                      unsigned flags, rsvd_plan_t** plan)
 {
     g_err.clear();
+    if (flags & PLAN_CPLX_OMEGA) return fail(RSVD_ERR_INVALID, "unknown plan flag");
+    if (flags & RSVD_PLAN_COMPLEX) {
+        if (!plan) return fail(RSVD_ERR_INVALID, "plan output pointer is null");
+        *plan = nullptr;
+        return complex_plan_create(probs, batch, dt, prec, flags, plan);
+    }
     return plan_create(probs, batch, dt, prec, flags, plan);
 }
 
@@ -1834,6 +2303,8 @@ int rsvd_plan_execute(rsvd_plan_t* plan, const void* const* A, void* const* U, v
                       double* discarded_weight, int64_t* k_kept, int* info, void* stream)
 {
     g_err.clear();
+    if (plan && plan->cx)
+        return complex_execute(plan, A, U, S, VT, discarded_weight, k_kept, info, (hipStream_t)stream, false);
     return plan_execute(plan, A, U, S, VT, discarded_weight, k_kept, info, (hipStream_t)stream);
 }
 
@@ -1886,11 +2357,21 @@ int rsvd_plan_profile(rsvd_plan_t* plan, const void* const* A, void* const* U, v
     plan->flags &= ~RSVD_PLAN_GRAPH;  // eager launches so that each can be timed
     Profiler prof;
     prof.s = s;
-    int rc = plan_execute(plan, A, U, S, VT, discarded_weight, k_kept, info, s);  // uploads descriptors
-    if (rc == RSVD_OK) {
-        plan->prof = &prof;
-        rc = enqueue(*plan, s);
-        plan->prof = nullptr;
+    int rc;
+    if (plan->cx) {
+        rc = complex_execute(plan, A, U, S, VT, discarded_weight, k_kept, info, s, true);  // uploads descriptors
+        if (rc == RSVD_OK) {
+            plan->prof = &prof;
+            rc = complex_enqueue(*plan, s);
+            plan->prof = nullptr;
+        }
+    } else {
+        rc = plan_execute(plan, A, U, S, VT, discarded_weight, k_kept, info, s);  // uploads descriptors
+        if (rc == RSVD_OK) {
+            plan->prof = &prof;
+            rc = enqueue(*plan, s);
+            plan->prof = nullptr;
+        }
     }
     plan->flags = saved;
     if (rc != RSVD_OK) return rc;
@@ -1913,8 +2394,9 @@ int rsvd_plan_profile(rsvd_plan_t* plan, const void* const* A, void* const* U, v
     // Jacobi work from the device counters of the profiled execute
     if (RSVD_PHASE_JACOBI < ncat) {
         std::vector<int> st(2);
-        for (const ProbHost& h : plan->probs) {
-            HIPCHK(hipMemcpy(st.data(), plan->ws + h.o_stats, 2 * sizeof(int), hipMemcpyDeviceToHost));
+        const rsvd_plan* jp = plan->cx ? plan->cx->inner : plan;
+        for (const ProbHost& h : jp->probs) {
+            HIPCHK(hipMemcpy(st.data(), jp->ws + h.o_stats, 2 * sizeof(int), hipMemcpyDeviceToHost));
             flops[RSVD_PHASE_JACOBI] += 2.0 * (2 * JAC_B) * (2 * JAC_B) * (h.C * (double)st[0] + ((double)h.C + h.R) * st[1]);
         }
     }
@@ -1964,6 +2446,7 @@ int rsvd_plan_postselect(rsvd_plan_t* plan, int64_t chi, int64_t* chi_s, void* s
 {
     g_err.clear();
     if (!plan) return fail(RSVD_ERR_INVALID, "plan is null");
+    if (plan->cx) return fail(RSVD_ERR_INVALID, "post-selection is not available for complex plans");
     if (!chi_s) return fail(RSVD_ERR_INVALID, "chi_s is null");
     if (chi < 0) return fail(RSVD_ERR_INVALID, "chi must be >= 0");
     if (!plan->blob_valid) return fail(RSVD_ERR_INVALID, "postselect needs a preceding rsvd_plan_execute");
@@ -1976,7 +2459,12 @@ int rsvd_plan_postselect(rsvd_plan_t* plan, int64_t chi, int64_t* chi_s, void* s
     return RSVD_OK;
 }
 
-int64_t rsvd_plan_workspace_bytes(const rsvd_plan_t* plan) { return plan ? (int64_t)plan->ws_bytes : 0; }
+int64_t rsvd_plan_workspace_bytes(const rsvd_plan_t* plan)
+{
+    if (!plan) return 0;
+    if (plan->cx) return (int64_t)(plan->cx->ws_bytes + plan->cx->inner->ws_bytes);
+    return (int64_t)plan->ws_bytes;
+}
 
 int rsvd_plan_tiles(const rsvd_plan_t* plan, int32_t* tiles, int64_t cap, int64_t* count)
 {

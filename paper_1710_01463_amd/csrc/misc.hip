@@ -104,6 +104,19 @@ __global__ __launch_bounds__(256) void omega_kernel(const OmegaDesc* __restrict_
     const OmegaDesc& d = descs[b];
     const int64_t idx = (int64_t)wi_.y * 256 + threadIdx.x;
     const int l = d.l, n = d.n;
+    if (d.complex_embed) {
+        // entry (i, j) of the complex test matrix -> its 2 x 2 real block
+        if (idx >= (int64_t)n * l) return;
+        const int i = (int)(idx / l), j = (int)(idx % l);
+        double re, im;
+        gaussian_complex(d.seed, (uint32_t)i, (uint32_t)j, &re, &im);
+        const int64_t ld = 2 * (int64_t)l;
+        store_elem(d.Om, d.elem, (int64_t)i * ld + j, re);
+        store_elem(d.Om, d.elem, (int64_t)i * ld + l + j, -im);
+        store_elem(d.Om, d.elem, (int64_t)(n + i) * ld + j, im);
+        store_elem(d.Om, d.elem, (int64_t)(n + i) * ld + l + j, re);
+        return;
+    }
     const int64_t pairs = (int64_t)((n + 1) / 2) * l;
     if (idx >= pairs) return;
     const int ip = (int)(idx / l), j = (int)(idx % l);
@@ -118,6 +131,34 @@ hipError_t launch_omega(const OmegaDesc* d, const int* blk_begin, int nprob, int
 {
     if (total_blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(omega_kernel, dim3(total_blocks), dim3(256), 0, s, d, blk_begin, nprob);
+    return hipGetLastError();
+}
+
+// At = [[Ar, -Ai], [Ai, Ar]] from the interleaved complex A: thread = one complex entry.
+__global__ __launch_bounds__(256) void embed_complex_kernel(const CEmbedDesc* __restrict__ descs,
+                                                            const int* __restrict__ blk_begin, int nprob)
+{
+    const int2 wi_ = wg_item(blk_begin, blockIdx.x);
+    const CEmbedDesc& d = descs[wi_.x];
+    const int64_t idx = (int64_t)wi_.y * 256 + threadIdx.x;
+    const int m = d.m, n = d.n;
+    if (idx >= (int64_t)m * n) return;
+    const int i = (int)(idx / n), j = (int)(idx % n);
+    const GLB double* a = to_glb(d.A) + 2 * ((int64_t)i * d.lda + j);
+    const double re = a[0], im = a[1];
+    GLB double* t = to_glb(d.At);
+    const int64_t ld = d.ldt;
+    t[(int64_t)i * ld + j] = re;
+    t[(int64_t)i * ld + n + j] = -im;
+    t[(int64_t)(m + i) * ld + j] = im;
+    t[(int64_t)(m + i) * ld + n + j] = re;
+}
+
+hipError_t launch_embed_complex(const CEmbedDesc* d, const int* blk_begin, int nprob, int total_blocks,
+                                hipStream_t s)
+{
+    if (total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(embed_complex_kernel, dim3(total_blocks), dim3(256), 0, s, d, blk_begin, nprob);
     return hipGetLastError();
 }
 

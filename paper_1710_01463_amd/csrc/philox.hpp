@@ -59,3 +59,23 @@ __device__ __forceinline__ void gaussian_pair(uint64_t seed, uint32_t ip, uint32
     *g_even = r * cs;
     *g_odd = r * sn;
 }
+
+// Complex entry (i, j) of the circular Gaussian test matrix of the complex
+// path: the Box-Muller pair of counter (i, j, 1, 0) (third word 1, so these
+// draws never share a counter with the real ones) as real and imaginary
+// parts, each divided by sqrt(2) so that E|w|^2 = 1.
+__device__ __forceinline__ void gaussian_complex(uint64_t seed, uint32_t i, uint32_t j, double* re, double* im)
+{
+    PhiloxWords x = philox4x32_10(i, j, 1u, 0u, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+    uint64_t a = ((uint64_t)x.w[0] << 32) | x.w[1];
+    uint64_t b = ((uint64_t)x.w[2] << 32) | x.w[3];
+    double u1 = 1.0 - (double)(a >> 11) * 0x1.0p-53;
+    double u2 = (double)(b >> 11) * 0x1.0p-53;
+    double r = sqrt(-2.0 * log(u1));
+    double ang = 2.0 * M_PI * u2;
+    double sn, cs;
+    sincos(ang, &sn, &cs);
+    const double s2 = sqrt(2.0);
+    *re = r * cs / s2;
+    *im = r * sn / s2;
+}

@@ -501,7 +501,16 @@ hipError_t launch_trsm_upper(const QrDesc* d, const int* row_begin, int nprob, i
 // One workgroup per flagged problem: in-place Householder QR of a copy of M in
 // Qout, then the explicit thin Q formed in place from the reflectors, and the
 // sign convention diag(R) >= 0.  Always orthonormal, also for rank-deficient M.
+//
+// M is row-major, so the work of each reflector is laid out along the rows:
+// for the trailing columns c > j, w_c = sum_i v_i M_ic and M_ic -= tau v_i w_c
+// are computed with lanes on consecutive columns (coalesced row segments; v_i
+// is one broadcast load per row) and the waves split the rows into groups
+// when the trailing block is narrower than the workgroup, the groups' partial
+// sums meeting in LDS.
 constexpr int HH_MAXL = 2048;
+constexpr int HH_T = 512;
+constexpr int HH_W = HH_T / 64;
 
 __device__ __forceinline__ double block_sum(double v, double* red)
 {
@@ -510,27 +519,62 @@ __device__ __forceinline__ double block_sum(double v, double* red)
     __syncthreads();
     if (lane == 0) red[wave] = v;
     __syncthreads();
-    double s = (red[0] + red[1]) + (red[2] + red[3]);
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < HH_W; ++w) s += red[w];
     return s;
 }
 
-__global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restrict__ descs)
+// Applies the reflector I - tau v v^T (v = (1, A[j+1:, j])) to the columns
+// c0 <= c < l of A (rows j..rows-1).  Called by all threads; part holds
+// HH_W x 64 partial sums.
+__device__ void hh_apply(GLB double* __restrict__ A, int rows, int l, int j, int c0, double tau, double* part)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int cb = c0; cb < l; cb += 64 * HH_W) {
+        const int nchunk = min(HH_W, (l - cb + 63) / 64);  // 64-column chunks in this pass
+        const int groups = HH_W / nchunk;                  // row groups per chunk
+        const int chunk = wave % nchunk, g = wave / nchunk;
+        const int c = cb + 64 * chunk + lane;
+        const bool act = g < groups && c < l;
+        // row j (v_j = 1) belongs to group 0; all reads of the block precede the barrier
+        double w = (act && g == 0) ? A[(int64_t)j * l + c] : 0.0;
+        if (act) {
+            for (int i = j + 1 + g; i < rows; i += groups) w = fma(A[(int64_t)i * l + j], A[(int64_t)i * l + c], w);
+        }
+        __syncthreads();  // part is free
+        part[wave * 64 + lane] = w;
+        __syncthreads();
+        if (act) {
+            // every group forms the same total (same order), so no broadcast is needed
+            double tot = 0.0;
+            for (int q = 0; q < groups; ++q) tot += part[(q * nchunk + chunk) * 64 + lane];
+            tot *= tau;
+            if (g == 0) A[(int64_t)j * l + c] -= tot;
+            for (int i = j + 1 + g; i < rows; i += groups) A[(int64_t)i * l + c] -= tot * A[(int64_t)i * l + j];
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(HH_T) void householder_kernel(const QrDesc* __restrict__ descs)
 {
     __shared__ double tau_s[HH_MAXL];
     __shared__ double beta_s[HH_MAXL];
-    __shared__ double red[4];
+    __shared__ double red[HH_W];
+    __shared__ double part[HH_W * 64];
     const QrDesc& d = descs[blockIdx.x];
     if (d.Qout == nullptr || !*to_glb(d.flag)) return;
     const int rows = d.rows, l = d.l;
     GLB double* __restrict__ A = to_glb(d.Qout);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
 
-    for (int64_t e = tid; e < (int64_t)rows * l; e += 256) A[e] = ld_elem(d.Min, d.min_elem, e);
+    for (int64_t e = tid; e < (int64_t)rows * l; e += HH_T) A[e] = ld_elem(d.Min, d.min_elem, e);
     __syncthreads();
 
     for (int j = 0; j < l; ++j) {
         double p = 0.0;
-        for (int i = j + 1 + tid; i < rows; i += 256) {
+        for (int i = j + 1 + tid; i < rows; i += HH_T) {
             const double x = A[(int64_t)i * l + j];
             p = fma(x, x, p);
         }
@@ -541,7 +585,7 @@ __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restri
             beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
             tau = (beta - alpha) / beta;
             const double scal = 1.0 / (alpha - beta);
-            for (int i = j + 1 + tid; i < rows; i += 256) A[(int64_t)i * l + j] *= scal;
+            for (int i = j + 1 + tid; i < rows; i += HH_T) A[(int64_t)i * l + j] *= scal;
         }
         __syncthreads();
         if (tid == 0) {
@@ -550,36 +594,18 @@ __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restri
             beta_s[j] = beta;
         }
         __syncthreads();
-        if (tau != 0.0) {
-            for (int c = j + 1 + wave; c < l; c += 4) {
-                double s = (lane == 0) ? A[(int64_t)j * l + c] : 0.0;
-                for (int i = j + 1 + lane; i < rows; i += 64) s = fma(A[(int64_t)i * l + j], A[(int64_t)i * l + c], s);
-                s = wave_sum(s) * tau;
-                if (lane == 0) A[(int64_t)j * l + c] -= s;
-                for (int i = j + 1 + lane; i < rows; i += 64) A[(int64_t)i * l + c] -= s * A[(int64_t)i * l + j];
-            }
-        }
-        __syncthreads();
+        if (tau != 0.0) hh_apply(A, rows, l, j, j + 1, tau, part);
     }
     // form Q in place from the reflectors, last one first
     for (int j = l - 1; j >= 0; --j) {
         const double tau = tau_s[j];
-        if (tau != 0.0) {
-            for (int c = j + 1 + wave; c < l; c += 4) {
-                double s = (lane == 0) ? A[(int64_t)j * l + c] : 0.0;
-                for (int i = j + 1 + lane; i < rows; i += 64) s = fma(A[(int64_t)i * l + j], A[(int64_t)i * l + c], s);
-                s = wave_sum(s) * tau;
-                if (lane == 0) A[(int64_t)j * l + c] -= s;
-                for (int i = j + 1 + lane; i < rows; i += 64) A[(int64_t)i * l + c] -= s * A[(int64_t)i * l + j];
-            }
-        }
-        __syncthreads();
-        for (int i = j + 1 + tid; i < rows; i += 256) A[(int64_t)i * l + j] *= -tau;
+        if (tau != 0.0) hh_apply(A, rows, l, j, j + 1, tau, part);
+        for (int i = j + 1 + tid; i < rows; i += HH_T) A[(int64_t)i * l + j] *= -tau;
         if (tid == 0) A[(int64_t)j * l + j] = 1.0 - tau;
-        for (int i = tid; i < j; i += 256) A[(int64_t)i * l + j] = 0.0;
+        for (int i = tid; i < j; i += HH_T) A[(int64_t)i * l + j] = 0.0;
         __syncthreads();
     }
-    for (int64_t e = tid; e < (int64_t)rows * l; e += 256) {
+    for (int64_t e = tid; e < (int64_t)rows * l; e += HH_T) {
         const int c = (int)(e % l);
         if (beta_s[c] < 0.0) A[e] = -A[e];
     }
@@ -639,7 +665,7 @@ hipError_t init_qr_kernels()
 hipError_t launch_householder(const QrDesc* d, int nprob, hipStream_t s)
 {
     if (nprob <= 0) return hipSuccess;
-    hipLaunchKernelGGL(householder_kernel, dim3(nprob), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(householder_kernel, dim3(nprob), dim3(HH_T), 0, s, d);
     return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@ import torch
 
 from . import _lib as L
 
-_DT = {torch.float64: L.RSVD_F64, torch.float32: L.RSVD_F32}
+_DT = {torch.float64: L.RSVD_F64, torch.float32: L.RSVD_F32, torch.complex128: L.RSVD_F64}
 
 
 def _stream():
@@ -25,8 +25,8 @@ def _check_matrix(A):
         raise ValueError("A must be a 2-D torch tensor")
     if A.device.type != "cuda":
         raise ValueError("A must be on a GPU device")
-    if A.dtype not in _DT:
-        raise ValueError("A must be float64 or float32")
+    if A.dtype not in (torch.float64, torch.float32):
+        raise ValueError("A must be float64 or float32 (complex matrices go through a Plan)")
     if A.stride(1) != 1:
         A = A.contiguous()
     return A
@@ -35,7 +35,7 @@ def _check_matrix(A):
 def _outputs(m, n, k, dtype, device):
     kk = min(k, m, n)
     U = torch.empty((m, kk), dtype=dtype, device=device)
-    S = torch.empty((kk,), dtype=dtype, device=device)
+    S = torch.empty((kk,), dtype=torch.float64 if dtype == torch.complex128 else dtype, device=device)
     VT = torch.empty((kk, n), dtype=dtype, device=device)
     return U, S, VT
 
@@ -135,10 +135,12 @@ class Plan:
     problems: list of dicts with keys m, n, k and (RSVD) p, q, seed, and
     optionally delta.  Outputs are allocated once by the plan and reused by
     every execute, so repeated executes on the same inputs upload nothing.
+    dtype torch.complex128 makes a complex plan (RSVD_PLAN_COMPLEX): A, U, VT
+    complex, S real.
     """
 
     def __init__(self, problems, dtype=torch.float64, prec="f64", fullsvd=False, graph=True,
-                 save=False, refine=True, tune=False, device="cuda"):
+                 save=False, refine=True, tune=False, round_launches=False, block_krylov=False, device="cuda"):
         self.dtype = dtype
         self.device = torch.device(device)
         self.fullsvd = fullsvd
@@ -158,7 +160,9 @@ class Plan:
             arr[i].ldvt = 0
         flags = (L.PLAN_FULLSVD if fullsvd else 0) | (L.PLAN_GRAPH if graph else 0) | \
                 (L.PLAN_SAVE if save else 0) | (0 if refine else L.PLAN_NO_REFINE) | \
-                (L.PLAN_TUNE if tune else 0)
+                (L.PLAN_TUNE if tune else 0) | (L.PLAN_ROUND_LAUNCHES if round_launches else 0) | \
+                (L.PLAN_BLOCK_KRYLOV if block_krylov else 0) | \
+                (L.PLAN_COMPLEX if dtype == torch.complex128 else 0)
         h = ctypes.c_void_p()
         L.check(L.lib().rsvd_plan_create(arr, n, _DT[dtype], L.PREC[prec], flags, ctypes.byref(h)))
         self._h = h
