@@ -226,6 +226,18 @@ typedef struct rsvd_plan rsvd_plan_t;
  * min(m, n) <= 1024).  Not with RSVD_PLAN_SAVE, RSVD_PLAN_TUNE (the shape
  * heuristic picks the tiles) or rsvd_plan_postselect. */
 #define RSVD_PLAN_COMPLEX 128u
+/* Blocked Householder fallback: when a Cholesky QR breaks down (a pivot below
+ * 1e-13 of its diagonal entry, i.e. a basis too ill-conditioned for the Gram
+ * matrix), the problem's basis is re-orthonormalised by Householder QR.  By
+ * default the plan takes the blocked form (panels of 16 columns in compact WY
+ * form, the trailing updates as FP64 MFMA products spread over many
+ * workgroups; two launches per panel) when max(m, n) (k + p)^2 of some problem
+ * is at least 2^27, and the one-workgroup-per-problem form otherwise (one
+ * launch; cheaper when no problem breaks down).  This flag asks for the
+ * blocked form for every size.  Both give Q with diag(R) >= 0 and agree to
+ * rounding.  The blocked form needs max(m, n) <= 2048 for every problem and is
+ * not used otherwise. */
+#define RSVD_PLAN_BLOCKED_QR 256u
 
 /* Validates the problems, sizes and allocates the plan's device workspace.
  * Returns RSVD_ERR_INVALID for bad problem descriptions. */

@@ -13,7 +13,7 @@ RSVD_OK, RSVD_ERR_INVALID, RSVD_ERR_ALLOC, RSVD_ERR_HIP, RSVD_ERR_NONFINITE, RSV
 RSVD_F64, RSVD_F32 = 0, 1
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 PLAN_FULLSVD, PLAN_GRAPH, PLAN_SAVE, PLAN_NO_REFINE, PLAN_TUNE, PLAN_ROUND_LAUNCHES = 1, 2, 4, 8, 16, 32
-PLAN_BLOCK_KRYLOV, PLAN_COMPLEX = 64, 128
+PLAN_BLOCK_KRYLOV, PLAN_COMPLEX, PLAN_BLOCKED_QR = 64, 128, 256
 
 PHASES = ["stage", "omega", "sketch", "gram", "chol", "trsm", "householder", "project", "jacobi",
           "finish", "backproj", "signfix", "other", "bw_gemm", "bw_small"]

@@ -77,6 +77,12 @@ hipError_t launch_trsm(const QrDesc* d, const int* row_begin, int nprob, int tot
 hipError_t init_qr_kernels();
 // Householder QR of Min into Qout for the problems whose flag is set.
 hipError_t launch_householder(const QrDesc* d, int nprob, hipStream_t s);
+// The same QR by panels of 16 columns (compact WY): 2 ceil(max_l / 16) launches,
+// the trailing updates spread over 64-column tiles.  Uses G (the panels' T
+// factors) and D (tau, beta) of each descriptor as scratch.  Every problem's
+// rows must be <= householder_blocked_rows_max() (hipErrorInvalidValue).
+hipError_t launch_householder_blocked(const QrDesc* d, int nprob, int max_l, int max_rows, hipStream_t s);
+int householder_blocked_rows_max();
 // Adjoint helpers on QrDesc fields: L holds R (l x l, row-major) = Q^T M of a
 // stage; tri_prep zeroes its strictly lower part and writes the diagonal-block
 // inverses of L = R^T into D.  trsm_upper replaces Qout (rows x l) by

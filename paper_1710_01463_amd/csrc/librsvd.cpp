@@ -74,6 +74,11 @@ constexpr int JAC_CROSS_MIN_NB = 16;
 // per-task release/acquire (an L2 write-back and invalidate on the XCD)
 // costs more than the launch boundaries it replaces.
 constexpr int JAC_PERSISTENT_MAX_PAIRS = 64;
+// Plans with max(m, n) l^2 at least this large take the blocked Householder
+// fallback: the one-workgroup form moves about 8 max(m, n) l^2 bytes per
+// factorisation through one CU, while the blocked form costs two launches per
+// 16-column panel even when no problem breaks down.
+constexpr double HH_BLOCKED_MIN_COST = (double)(1 << 27);
 constexpr int64_t JAC_PERSISTENT_MAX_TASKS = 1 << 18;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -189,6 +194,8 @@ struct rsvd_plan {
     std::vector<IdxLaunch> kcopy; // per stage: copy of the stage's basis into the Krylov block (even stages)
     GemmLaunch g_kgram1, g_kgram2;
     IdxLaunch k_qr[2], k_trsm[2];
+    bool hh_blocked = false;      // the Householder fallback runs in blocked form
+    int hh_rows = 0;              // largest number of rows of any orthonormalised basis
     bool jac_persistent = false;  // the Jacobi phase is one persistent launch
     int jac_grid = 0;             // its workgroups
     size_t off_sched = 0;         // its task counter and error flag (2 ints, cleared every execute)
@@ -1168,6 +1175,13 @@ int gemm(rsvd_plan& P, const GemmLaunch& g, hipStream_t s, int cat)
     return RSVD_OK;
 }
 
+// Householder fallback of one orthonormalisation site, blocked or not.
+hipError_t householder(const rsvd_plan& P, const QrDesc* d, hipStream_t s)
+{
+    if (P.hh_blocked) return launch_householder_blocked(d, P.nprob, P.max_l, P.hh_rows, s);
+    return launch_householder(d, P.nprob, s);
+}
+
 // The full launch sequence of one execute (captured into a graph when asked).
 int enqueue(rsvd_plan& P, hipStream_t s)
 {
@@ -1202,7 +1216,7 @@ int enqueue(rsvd_plan& P, hipStream_t s)
                         launch_trsm(dp<QrDesc>(P, t2.off_desc), dp<int>(P, t2.off_begin), np, t2.total, 0, E_F64, P.max_l, s));
             }
             // Householder for the problems whose Cholesky QR broke down
-            PLAUNCH(RSVD_PHASE_HOUSEHOLDER, 0.0, launch_householder(dp<QrDesc>(P, q1.off_desc), np, s));
+            PLAUNCH(RSVD_PHASE_HOUSEHOLDER, 0.0, householder(P, dp<QrDesc>(P, q1.off_desc), s));
             if (P.krylov && P.kcopy[st].total > 0)
                 PLAUNCH(RSVD_PHASE_OTHER, 0.0,
                         launch_copy_f64(dp<CopyDesc>(P, P.kcopy[st].off_desc), dp<int>(P, P.kcopy[st].off_begin), np,
@@ -1219,7 +1233,7 @@ int enqueue(rsvd_plan& P, hipStream_t s)
             PLAUNCH(RSVD_PHASE_TRSM, 0.0,
                     launch_trsm(dp<QrDesc>(P, P.k_trsm[1].off_desc), dp<int>(P, P.k_trsm[1].off_begin), np,
                                 P.k_trsm[1].total, 0, E_F64, P.max_l, s));
-            PLAUNCH(RSVD_PHASE_HOUSEHOLDER, 0.0, launch_householder(dp<QrDesc>(P, P.k_qr[0].off_desc), np, s));
+            PLAUNCH(RSVD_PHASE_HOUSEHOLDER, 0.0, householder(P, dp<QrDesc>(P, P.k_qr[0].off_desc), s));
         }
         if (P.any_lq) {
             if ((rc = gemm(P, P.g_lqbt, s, RSVD_PHASE_PROJECT)) != RSVD_OK) return rc;
@@ -1233,7 +1247,7 @@ int enqueue(rsvd_plan& P, hipStream_t s)
             PLAUNCH(RSVD_PHASE_TRSM, 0.0,
                     launch_trsm(dp<QrDesc>(P, P.lq_trsm[1].off_desc), dp<int>(P, P.lq_trsm[1].off_begin), np,
                                 P.lq_trsm[1].total, 0, E_F64, P.max_l, s));
-            PLAUNCH(RSVD_PHASE_HOUSEHOLDER, 0.0, launch_householder(dp<QrDesc>(P, P.lq_qr[0].off_desc), np, s));
+            PLAUNCH(RSVD_PHASE_HOUSEHOLDER, 0.0, householder(P, dp<QrDesc>(P, P.lq_qr[0].off_desc), s));
             if ((rc = gemm(P, P.g_lqx, s, RSVD_PHASE_PROJECT)) != RSVD_OK) return rc;
         }
         if ((rc = gemm(P, P.g_b, s, RSVD_PHASE_PROJECT)) != RSVD_OK) return rc;
@@ -1633,6 +1647,18 @@ int plan_setup(rsvd_plan* P, const rsvd_problem_t* probs, int64_t batch, rsvd_dt
         P->max_q = std::max<int>(P->max_q, (int)h.q);
     }
     if (!fullsvd) P->max_sweeps = P->max_l > JAC_WIDE_L ? JAC_MAX_SWEEPS_RSVD_WIDE : JAC_MAX_SWEEPS_RSVD;
+    if (!fullsvd) {
+        // blocked Householder fallback for large bases (the one-workgroup form
+        // reads the trailing matrix once per column), or when asked for
+        double cost = 0.0;
+        for (const ProbHost& h : P->probs) {
+            const double rows = (double)std::max(h.m, h.n), w = (double)std::max(h.l, h.R);
+            P->hh_rows = std::max<int>(P->hh_rows, (int)std::max(h.m, h.n));
+            cost = std::max(cost, rows * w * w);
+        }
+        P->hh_blocked = P->hh_rows <= householder_blocked_rows_max() &&
+                        ((flags & RSVD_PLAN_BLOCKED_QR) || cost >= HH_BLOCKED_MIN_COST);
+    }
     layout(*P);
     return RSVD_OK;
 }
@@ -1892,7 +1918,8 @@ int complex_plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t
     P->cx = new ComplexExt();
     ComplexExt& X = *P->cx;
     const unsigned inner_flags =
-        (flags & (RSVD_PLAN_FULLSVD | RSVD_PLAN_NO_REFINE | RSVD_PLAN_ROUND_LAUNCHES | RSVD_PLAN_BLOCK_KRYLOV)) |
+        (flags & (RSVD_PLAN_FULLSVD | RSVD_PLAN_NO_REFINE | RSVD_PLAN_ROUND_LAUNCHES | RSVD_PLAN_BLOCK_KRYLOV |
+                  RSVD_PLAN_BLOCKED_QR)) |
         (full ? 0u : PLAN_CPLX_OMEGA);
     int rc = plan_create(in.data(), batch, RSVD_F64, prec, inner_flags, &X.inner);
     if (rc != RSVD_OK) {

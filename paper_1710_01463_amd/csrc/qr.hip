@@ -611,6 +611,356 @@ __global__ __launch_bounds__(HH_T) void householder_kernel(const QrDesc* __restr
     }
 }
 
+// ---------------------------------------------------------------- blocked Householder
+// The same factorisation as householder_kernel, by panels of HB = 16 columns
+// (compact WY form, Schreiber and Van Loan): the product of a panel's
+// reflectors is H = H_1 ... H_bw = I - V T V^T, with V (rows x bw, unit lower
+// trapezoidal, stored below the diagonal of the panel) and T (bw x bw upper
+// triangular).  A panel is factored in registers by one workgroup; the rest of
+// the matrix is updated by H^T (factorisation) or H (forming Q, last panel
+// first) as two FP64 MFMA products per 64-column tile, W = V^T C and
+// C -= V (X W) with X = T^T or T, one workgroup per tile, so the update of one
+// problem spreads over many CUs and reads its columns once per panel instead of
+// once per column.
+//
+// One launch per panel and phase (hb_kernel, blockIdx.x = tile, blockIdx.y =
+// problem):
+//   factor, launch J:  tiles over columns [16 J, l): J = 0 copies M in, J > 0
+//                      applies panel J-1; then tile 0 factors panel J.
+//   form Q, launch J (J = P-2 .. -1): tiles over columns [16 (J+1), l):
+//                      tile 0 turns panel J+1 into its Q columns (E - V T V_top^T,
+//                      zero above), then every tile applies panel J (J >= 0), or
+//                      at J = -1 the sign convention diag(R) >= 0.
+// T of panel J is kept in G (offset 256 J, row-major with stride bw), tau and
+// beta in D (D[c], D[l + c]).
+constexpr int HB = 16;
+constexpr int HB_TW = 64;
+constexpr int HB_T = 512;
+constexpr int HB_G = HB_T / HB;  // row groups of the panel layout
+enum { HB_FACTOR = 0, HB_QFORM = 1 };
+
+struct HbLds {
+    double wpart[4 * 64 * 4];  // W partial sums of the second row half
+    double W[HB * HB_TW];      // W = V^T C, then Y = X W
+    double red[HB_T / 64][HB]; // panel reductions, one row per wave
+    double T[HB * HB];
+    double tau[HB], beta[HB];
+    double Wc[HB * HB];        // T V_top^T for the Q columns of a panel
+    double scal[2];
+};
+
+// V[r][k] of the panel at column pc with bw columns (r >= pc): 1 on the
+// diagonal, the stored reflector entries below, 0 above and for k >= bw.
+__device__ __forceinline__ double hb_v(const GLB double* A, int64_t l, int rows, int pc, int bw, int r, int k)
+{
+    const int d = r - pc;
+    const bool below = d > k && k < bw && r < rows;
+    const double x = A[below ? (int64_t)r * l + pc + k : 0];
+    return below ? x : ((d == k && k < bw) ? 1.0 : 0.0);
+}
+
+// Applies I - V X V^T to the columns [c0, c1) of rows [pc, rows), with X = T^T
+// (trans) or T: W = V^T C, Y = X W, C -= V Y.  All 512 threads; the tile is at
+// most 64 columns wide and lies right of the panel.
+__device__ void hb_update(GLB double* __restrict__ A, int64_t l, int rows, int pc, int bw,
+                          const GLB double* __restrict__ Tg, bool trans, int c0, int c1, HbLds& s)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int cb = wave & 3, h = wave >> 2;
+    const int c = c0 + 16 * cb + l16;
+    const bool cok = c < c1;
+    // ---- W = V^T C: D[k][col] = sum_r V[r][k] C[r][col], K = rows, 4 rows per MFMA
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int rb = pc + 4 * h; rb < rows; rb += 8) {
+        const int r = rb + lq;
+        const double av = hb_v(A, l, rows, pc, bw, r, l16);
+        const double bv = ld_or0<double>(A, (int64_t)r * l + c, r < rows && cok);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    if (h == 1) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s.wpart[(cb * 64 + lane) * 4 + q] = acc[q];
+    }
+    __syncthreads();
+    if (h == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s.W[(lq + 4 * q) * HB_TW + 16 * cb + l16] = acc[q] + s.wpart[(cb * 64 + lane) * 4 + q];
+    }
+    __syncthreads();
+    // ---- Y = X W (16 x 64), two rows per thread, written over W after a barrier
+    double y[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int k = 2 * wave + u;
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < HB; ++j) {
+            const bool ok = k < bw && j < bw;
+            const double x = Tg[ok ? (trans ? j * bw + k : k * bw + j) : 0];
+            t = fma(ok ? x : 0.0, s.W[j * HB_TW + lane], t);
+        }
+        y[u] = t;
+    }
+    __syncthreads();
+    s.W[(2 * wave) * HB_TW + lane] = y[0];
+    s.W[(2 * wave + 1) * HB_TW + lane] = y[1];
+    __syncthreads();
+    // ---- C -= V Y: 16-row blocks, D[row][col] = sum_k V[row][k] Y[k][col], 4 MFMAs (K = 16)
+    double bvv[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) bvv[m] = s.W[(4 * m + lq) * HB_TW + 16 * cb + l16];
+    for (int rb = pc + 16 * h; rb < rows; rb += 32) {
+        double av[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) av[m] = hb_v(A, l, rows, pc, bw, rb + l16, 4 * m + lq);
+        dbl4 p = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) p = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bvv[m], p, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = rb + lq + 4 * q;
+            if (r < rows && cok) A[(int64_t)r * l + c] -= p[q];
+        }
+    }
+    __syncthreads();
+}
+
+// Sum over the 32 row groups of the panel layout (thread = group * 16 + column):
+// the per-column totals meet in LDS and every thread reads the total of column
+// col.  Two barriers; red is free again on return.
+__device__ __forceinline__ double hb_colsum(double v, double (*red)[HB], int col)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (lane < HB) red[wave][lane] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < HB_T / 64; ++w) t += red[w][col];
+    __syncthreads();
+    return t;
+}
+
+// Factors the panel at column pc (bw <= 16 columns, rows [pc, rows)) in
+// registers: RPT rows per thread, rows - pc <= 32 RPT.
+template <int RPT>
+__device__ void hb_panel(GLB double* __restrict__ A, int64_t l, int rows, int pc, int bw, GLB double* __restrict__ Tg,
+                         GLB double* __restrict__ Dg, HbLds& s)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int c = tid & 15, g = tid >> 4;
+    const bool cok = c < bw;
+    double x[RPT];
+#pragma unroll
+    for (int i0 = 0; i0 < RPT; i0 += 16) {
+#pragma unroll
+        for (int i = i0; i < i0 + 16 && i < RPT; ++i) {
+            const int r = pc + g + HB_G * i;
+            x[i] = ld_or0<double>(A, (int64_t)r * l + pc + c, r < rows && cok);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (tid < HB * HB) s.T[tid] = 0.0;
+    // Register row i of this thread is row pc + g + 32 i.  For i >= 1 that row
+    // lies below the diagonal of every panel column (j < 16 < 32), so only
+    // i = 0 needs the row tests; rows past the end hold zeros.
+    for (int j = 0; j < bw; ++j) {
+        const bool below0 = g > j, diag0 = g == j;
+        // squared norm of column j below the diagonal, and the diagonal entry alpha
+        double p = below0 ? x[0] * x[0] : 0.0;
+#pragma unroll
+        for (int i = 1; i < RPT; ++i) p = fma(x[i], x[i], p);
+        p = c == j ? p : 0.0;
+        if (c == j && diag0) s.scal[0] = x[0];
+        const double xn2 = hb_colsum(p, s.red, j);
+        const double alpha = s.scal[0];
+        double tau = 0.0, beta = alpha, sc = 1.0;
+        if (xn2 > 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+            tau = (beta - alpha) / beta;
+            sc = 1.0 / (alpha - beta);
+        }
+        {
+            const double scl = c == j ? sc : 1.0;  // x * 1.0 == x: no branch over the rows
+            x[0] *= below0 ? scl : 1.0;
+#pragma unroll
+            for (int i = 1; i < RPT; ++i) x[i] *= scl;
+        }
+        // v_j at this thread's rows comes from the lane of column j in the same
+        // row group (all lanes shuffle; column j itself is not changed below),
+        // in chunks of 16 rows so that not every shuffle result is held at once
+        double dot;
+        {
+            const double xv = __shfl(x[0], (lane & 48) | j, 64);
+            dot = (below0 ? xv : (diag0 ? 1.0 : 0.0)) * x[0];
+        }
+#pragma unroll
+        for (int i0 = 1; i0 < RPT; i0 += 16) {
+#pragma unroll
+            for (int i = i0; i < i0 + 16 && i < RPT; ++i) dot = fma(__shfl(x[i], (lane & 48) | j, 64), x[i], dot);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // s_c = v_j^T (column c): the reflector's dots for c > j, V^T v_j for c < j
+        const double sc_tot = hb_colsum(dot, s.red, c);
+        const double f = c > j ? tau * sc_tot : 0.0;
+        // the same shuffles as for the dots, recomputed: an opaque source lane keeps
+        // the compiler from holding all RPT shuffle results across the reduction
+        int src = (lane & 48) | j;
+        asm volatile("" : "+v"(src));
+        {
+            const double xv = __shfl(x[0], src, 64);
+            x[0] = fma(-f, below0 ? xv : (diag0 ? 1.0 : 0.0), x[0]);
+        }
+#pragma unroll
+        for (int i0 = 1; i0 < RPT; i0 += 16) {
+#pragma unroll
+            for (int i = i0; i < i0 + 16 && i < RPT; ++i) x[i] = fma(-f, __shfl(x[i], src, 64), x[i]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (c == j && g == j) x[0] = beta;
+        // T column j: T[j][j] = tau, T[k][j] = -tau sum_{k <= q < j} T[k][q] s_q
+        if (g == 0) s.red[0][c] = sc_tot;
+        __syncthreads();
+        if (tid < j) {
+            double t = 0.0;
+            for (int q = tid; q < j; ++q) t = fma(s.T[tid * HB + q], s.red[0][q], t);
+            s.T[tid * HB + j] = -tau * t;
+        }
+        if (tid == 0) {
+            s.T[j * HB + j] = tau;
+            s.tau[j] = tau;
+            s.beta[j] = beta;
+        }
+        __syncthreads();
+    }
+    // opaque copies, so that the row addresses of the loads are recomputed here
+    // instead of being kept live through the factorisation
+    int64_t ls = l;
+    int g2 = g;
+    asm volatile("" : "+s"(ls), "+v"(g2));
+#pragma unroll
+    for (int i0 = 0; i0 < RPT; i0 += 16) {
+#pragma unroll
+        for (int i = i0; i < i0 + 16 && i < RPT; ++i) {
+            const int r = pc + g2 + HB_G * i;
+            if (r < rows && cok) A[(int64_t)r * ls + pc + c] = x[i];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (tid < bw * bw) Tg[tid] = s.T[(tid / bw) * HB + tid % bw];
+    if (tid < bw) {
+        Dg[pc + tid] = s.tau[tid];
+        Dg[l + pc + tid] = s.beta[tid];
+    }
+    __syncthreads();
+}
+
+// Q columns of the panel at pc (bw columns) from its reflectors: rows < pc are
+// zero, rows >= pc are E - V (T V_top^T).  One row per thread at a time: a
+// row's reflector entries are read before its Q entries are written, and no
+// other thread touches that row.
+__device__ void hb_panel_q(GLB double* __restrict__ A, int64_t l, int rows, int pc, int bw,
+                           const GLB double* __restrict__ Tg, HbLds& s)
+{
+    const int tid = threadIdx.x;
+    if (tid < HB * HB) {
+        const int k = tid >> 4, cc = tid & 15;
+        double t = 0.0;
+        for (int j = 0; j < HB; ++j) {
+            const bool ok = k < bw && j < bw && cc < bw;
+            const double tk = Tg[ok ? k * bw + j : 0];
+            t = fma(ok ? tk : 0.0, ok ? hb_v(A, l, rows, pc, bw, pc + cc, j) : 0.0, t);
+        }
+        s.Wc[tid] = t;
+    }
+    __syncthreads();
+    for (int r = tid; r < rows; r += HB_T) {
+        double out[HB];
+#pragma unroll
+        for (int cc = 0; cc < HB; ++cc) out[cc] = (r - pc == cc) ? 1.0 : 0.0;
+        if (r >= pc) {
+            // k outermost, one reflector entry and one row of Wc at a time (a fully
+            // unrolled k x cc loop would hold all of Wc in registers)
+#pragma unroll 2
+            for (int k = 0; k < HB; ++k) {
+                const double vk = hb_v(A, l, rows, pc, bw, r, k);
+#pragma unroll
+                for (int cc = 0; cc < HB; ++cc) out[cc] = fma(-vk, s.Wc[k * HB + cc], out[cc]);
+            }
+        }
+#pragma unroll
+        for (int cc = 0; cc < HB; ++cc)
+            if (cc < bw) A[(int64_t)r * l + pc + cc] = out[cc];
+    }
+    __syncthreads();
+}
+
+template <int RPT>
+__global__ __launch_bounds__(HB_T) void hb_kernel(const QrDesc* __restrict__ descs, int J, int mode)
+{
+    __shared__ HbLds s;
+    const QrDesc& d = descs[blockIdx.y];
+    if (d.Qout == nullptr || !*to_glb(d.flag)) return;
+    const int rows = d.rows, l = d.l;
+    const int t = blockIdx.x;
+    const int lo = mode == HB_FACTOR ? HB * J : HB * (J + 1);
+    const int c0 = lo + HB_TW * t;
+    if (c0 >= l) return;
+    const int c1 = min(c0 + HB_TW, l);
+    GLB double* __restrict__ A = to_glb(d.Qout);
+    GLB double* __restrict__ G = to_glb(d.G);
+    GLB double* __restrict__ D = to_glb(d.D);
+    const int tid = threadIdx.x;
+    if (mode == HB_FACTOR) {
+        if (J == 0) {
+            const int lane = tid & 63, wave = tid >> 6;
+            for (int r = wave; r < rows; r += HB_T / 64)
+                if (c0 + lane < c1) A[(int64_t)r * l + c0 + lane] = ld_elem(d.Min, d.min_elem, (int64_t)r * l + c0 + lane);
+            __syncthreads();
+        } else {
+            hb_update(A, l, rows, HB * (J - 1), HB, G + HB * HB * (J - 1), true, c0, c1, s);
+        }
+        if (t == 0) hb_panel<RPT>(A, l, rows, lo, min(HB, l - lo), G + HB * HB * J, D, s);
+        return;
+    }
+    if (t == 0) hb_panel_q(A, l, rows, lo, min(HB, l - lo), G + HB * HB * (J + 1), s);
+    if (J >= 0) {
+        hb_update(A, l, rows, HB * J, HB, G + HB * HB * J, false, c0, c1, s);
+    } else {
+        const int lane = tid & 63, wave = tid >> 6;
+        const int cc = c0 + lane;
+        const bool neg = cc < c1 && D[cc < c1 ? l + cc : 0] < 0.0;
+        if (neg)
+            for (int r = wave; r < rows; r += HB_T / 64) A[(int64_t)r * l + cc] = -A[(int64_t)r * l + cc];
+    }
+}
+
+int householder_blocked_rows_max() { return HB_G * 64; }
+
+hipError_t launch_householder_blocked(const QrDesc* d, int nprob, int max_l, int max_rows, hipStream_t s)
+{
+    if (nprob <= 0 || max_l <= 0) return hipSuccess;
+    if (max_rows > householder_blocked_rows_max()) return hipErrorInvalidValue;
+    const int P = (max_l + HB - 1) / HB;
+    auto go = [&](int J, int mode) {
+        const int lo = mode == HB_FACTOR ? HB * J : HB * (J + 1);
+        const dim3 grid((max_l - lo + HB_TW - 1) / HB_TW, nprob);
+        if (max_rows <= HB_G * 16)
+            hipLaunchKernelGGL(hb_kernel<16>, grid, dim3(HB_T), 0, s, d, J, mode);
+        else if (max_rows <= HB_G * 32)
+            hipLaunchKernelGGL(hb_kernel<32>, grid, dim3(HB_T), 0, s, d, J, mode);
+        else
+            hipLaunchKernelGGL(hb_kernel<64>, grid, dim3(HB_T), 0, s, d, J, mode);
+        return hipGetLastError();
+    };
+    hipError_t e = hipSuccess;
+    for (int J = 0; J < P && e == hipSuccess; ++J) e = go(J, HB_FACTOR);
+    for (int J = P - 2; J >= -1 && e == hipSuccess; --J) e = go(J, HB_QFORM);
+    return e;
+}
+
 static size_t chol_lds_bytes(int max_l)
 {
     return (size_t)(((max_l + 1) & ~1) + (size_t)max_l * 17) * sizeof(double);  // g0, then Lp rows < l

@@ -140,7 +140,8 @@ class Plan:
     """
 
     def __init__(self, problems, dtype=torch.float64, prec="f64", fullsvd=False, graph=True,
-                 save=False, refine=True, tune=False, round_launches=False, block_krylov=False, device="cuda"):
+                 save=False, refine=True, tune=False, round_launches=False, block_krylov=False, blocked_qr=False,
+                 device="cuda"):
         self.dtype = dtype
         self.device = torch.device(device)
         self.fullsvd = fullsvd
@@ -161,7 +162,7 @@ class Plan:
         flags = (L.PLAN_FULLSVD if fullsvd else 0) | (L.PLAN_GRAPH if graph else 0) | \
                 (L.PLAN_SAVE if save else 0) | (0 if refine else L.PLAN_NO_REFINE) | \
                 (L.PLAN_TUNE if tune else 0) | (L.PLAN_ROUND_LAUNCHES if round_launches else 0) | \
-                (L.PLAN_BLOCK_KRYLOV if block_krylov else 0) | \
+                (L.PLAN_BLOCK_KRYLOV if block_krylov else 0) | (L.PLAN_BLOCKED_QR if blocked_qr else 0) | \
                 (L.PLAN_COMPLEX if dtype == torch.complex128 else 0)
         h = ctypes.c_void_p()
         L.check(L.lib().rsvd_plan_create(arr, n, _DT[dtype], L.PREC[prec], flags, ctypes.byref(h)))
