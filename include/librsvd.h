@@ -60,7 +60,8 @@ typedef enum {
     RSVD_ERR_ALLOC = -2,     /* device or pinned-host allocation failed */
     RSVD_ERR_HIP = -3,       /* a HIP runtime call failed */
     RSVD_ERR_NONFINITE = -4, /* ||A||_F^2 is not finite (NaN or Inf in A); outputs zero, k_kept = 0 */
-    RSVD_ERR_NOCONV = -5     /* Jacobi sweep cap reached; outputs are still filled */
+    RSVD_ERR_NOCONV = -5,    /* Jacobi sweep cap reached; outputs are still filled */
+    RSVD_ERR_SINGULAR = -6   /* single-view plans: Psi Q numerically rank deficient; outputs filled, unreliable */
 } rsvd_status_t;
 
 /* Storage type of A, U, S and VT. */
@@ -238,6 +239,28 @@ typedef struct rsvd_plan rsvd_plan_t;
  * rounding.  The blocked form needs max(m, n) <= 2048 for every problem and is
  * not used otherwise. */
 #define RSVD_PLAN_BLOCKED_QR 256u
+/* Single-view variant (the one-pass scheme named in the outlook, Sec. V, after
+ * Tropp, Yurtsever, Udell and Cevher): A is sketched once from both sides and
+ * the small matrix is recovered from the sketches alone.  With l = min(k + p,
+ * m, n) and s = min(2 l + 1, m):
+ *   Omega = the n x l Gaussian of the seed (as for the RSVD), Psi = the
+ *   transpose of the m x s Gaussian of the seed with its top bit flipped
+ *   (seed ^ 2^63, an independent Philox key);
+ *   Y = A Omega (the plan's sketch precision), W = Psi A (FP64);
+ *   Q = orth(Y) (Cholesky QR twice, Householder on breakdown);
+ *   X = (Psi Q)^+ W (FP64; from the normal equations of Psi Q, whose
+ *   condition number is about (sqrt(s) + sqrt(l)) / (sqrt(s) - sqrt(l)) for a
+ *   Gaussian Psi);
+ *   X = Utilde S V^T by the Jacobi of the RSVD, U = Q Utilde, canonical signs.
+ * q is ignored.  Q X is not a projection of A, so the discarded weight is the
+ * true error ||A - U S V^T||_F^2 of the kept triplets, evaluated from
+ * u_i^T A v_i by one more product with A (the truncation rule needs it): w =
+ * ||A||^2 - sum over kept i of (2 sigma_i u_i^T A v_i - sigma_i^2).  k_kept is
+ * the smallest k' >= 1 whose w is at most delta ||A||_F^2, at most k.  info
+ * RSVD_ERR_SINGULAR when the Cholesky factorisation of (Psi Q)^T (Psi Q)
+ * breaks down.  Not with RSVD_PLAN_FULLSVD, RSVD_PLAN_SAVE,
+ * RSVD_PLAN_BLOCK_KRYLOV, RSVD_PLAN_COMPLEX or rsvd_plan_postselect. */
+#define RSVD_PLAN_SINGLE_VIEW 512u
 
 /* Validates the problems, sizes and allocates the plan's device workspace.
  * Returns RSVD_ERR_INVALID for bad problem descriptions. */

@@ -10,10 +10,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librsvd.so")
 
 RSVD_OK, RSVD_ERR_INVALID, RSVD_ERR_ALLOC, RSVD_ERR_HIP, RSVD_ERR_NONFINITE, RSVD_ERR_NOCONV = 0, -1, -2, -3, -4, -5
+RSVD_ERR_SINGULAR = -6
 RSVD_F64, RSVD_F32 = 0, 1
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 PLAN_FULLSVD, PLAN_GRAPH, PLAN_SAVE, PLAN_NO_REFINE, PLAN_TUNE, PLAN_ROUND_LAUNCHES = 1, 2, 4, 8, 16, 32
-PLAN_BLOCK_KRYLOV, PLAN_COMPLEX, PLAN_BLOCKED_QR = 64, 128, 256
+PLAN_BLOCK_KRYLOV, PLAN_COMPLEX, PLAN_BLOCKED_QR, PLAN_SINGLE_VIEW = 64, 128, 256, 512
 
 PHASES = ["stage", "omega", "sketch", "gram", "chol", "trsm", "householder", "project", "jacobi",
           "finish", "backproj", "signfix", "other", "bw_gemm", "bw_small"]

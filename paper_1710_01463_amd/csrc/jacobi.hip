@@ -667,7 +667,8 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinDesc* __restrict__
                 tail[0] = normA2;
                 for (int j = 1; j <= k; ++j) {
                     const double sj = sig[perm_s[j - 1]];
-                    const double x = -sj * sj;
+                    // single view: keeping triplet i removes 2 sigma_i u_i^T A v_i - sigma_i^2
+                    const double x = d.cross ? sj * sj - to_glb(d.cross)[perm_s[j - 1]] : -sj * sj;
                     const double tsum = s + x;
                     if (fabs(s) >= fabs(x)) c += (s - tsum) + x; else c += (x - tsum) + s;
                     s = tsum;
@@ -698,6 +699,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const FinDesc* __restrict__
         }
         if (info == 0 && d.rot && to_glb(d.rot)[d.max_sweeps - 1] != 0) info = -5;  // sweep cap reached
         if (d.jac_err && *to_glb(d.jac_err) != 0) info = -3;  // the persistent Jacobi gave up waiting
+        if (info != -4 && d.sv_flag && *to_glb(d.sv_flag) != 0) info = -6;  // singular co-range system
         kk_s = kk;
         *to_glb(d.w_out) = w;
         *to_glb(d.kkept_out) = kk;

@@ -141,6 +141,8 @@ struct FinDesc {
     const double* normA2;
     const int* rot;    // Jacobi flags, to detect the sweep cap
     const int* jac_err; // error flag of the persistent Jacobi launch (may be null)
+    const double* cross; // single-view plans: 2 sigma_i u_i^T A v_i per Jacobi row (else null)
+    const int* sv_flag; // single-view plans: breakdown flag of the co-range system (else null)
     void* U;
     void* S;
     void* VT;
@@ -280,6 +282,18 @@ struct EyeDesc {
     int pad_;
 };
 hipError_t launch_eye(const EyeDesc* d, const int* blk_begin, int nprob, int total_blocks, hipStream_t s);
+
+// out[i] = alpha * sum_j X[i][j] Y[i][j] for the rows i < rows (row-major,
+// leading dimensions ldx, ldy); item map over groups of 4 rows, one wave per row.
+struct RowDotDesc {
+    const double* X;
+    const double* Y;
+    double* out;
+    int64_t ldx, ldy;
+    int rows, cols;
+    double alpha;
+};
+hipError_t launch_rowdot(const RowDotDesc* d, const int* blk_begin, int nprob, int total_blocks, hipStream_t s);
 
 // ---------------------------------------------------------------- adjoint
 // Elementwise steps of the reverse pass of one RSVD (cotangent staging, the

@@ -115,6 +115,11 @@ struct ProbHost {
     size_t o_bt, o_qb;  // B^T = A^T Q and its orthonormal factor Q_B (n x R, FP64), lq problems only
     size_t o_kraw, o_kq;  // block-Krylov plans: the power bases side by side (m x R) and their orthonormal basis
     size_t o_sgn;  // k canonical signs written by the sign fix (0 beyond k_kept)
+    // single-view plans: s = min(2 l + 1, m) rows of the co-range sketch; Psi^T (m x s),
+    // W = Psi A (s x n), Z = Psi Q (s x l, then its orthonormal factor in place), L^-T (l x l),
+    // Z^T W / its solve (l x n), F = A X^T (m x l), F^T Q (l x l), 2 sigma_i u_i^T A v_i (l)
+    int sv_s = 0;
+    size_t o_psi = 0, o_w = 0, o_z = 0, o_linv = 0, o_msv = 0, o_f = 0, o_ht = 0, o_cross = 0;
     // reverse pass (RSVD_PLAN_SAVE only)
     size_t o_bw_w[2], o_bw_vbt, o_bw_vts, o_bw_bb, o_bw_ut, o_bw_utb, o_bw_eu, o_bw_ev, o_bw_kp, o_bw_sb;
     int nchunks;
@@ -194,6 +199,9 @@ struct rsvd_plan {
     std::vector<IdxLaunch> kcopy; // per stage: copy of the stage's basis into the Krylov block (even stages)
     GemmLaunch g_kgram1, g_kgram2;
     IdxLaunch k_qr[2], k_trsm[2];
+    bool single_view = false;     // single-view variant (RSVD_PLAN_SINGLE_VIEW)
+    IdxLaunch omega_psi, sv_qr, sv_trsm_z, sv_trsm_i, sv_eye, sv_cross;
+    GemmLaunch g_sv_w, g_sv_z, g_sv_gram, g_sv_m, g_sv_x, g_sv_f, g_sv_ht;
     bool hh_blocked = false;      // the Householder fallback runs in blocked form
     int hh_rows = 0;              // largest number of rows of any orthonormalised basis
     bool jac_persistent = false;  // the Jacobi phase is one persistent launch
@@ -356,6 +364,17 @@ void layout(rsvd_plan& P)
         h.o_qb = h.lq ? take(sizeof(double) * n * h.R) : 0;
         h.o_kraw = P.krylov ? take(sizeof(double) * m * h.R) : 0;
         h.o_kq = P.krylov ? take(sizeof(double) * m * h.R) : 0;
+        if (P.single_view) {
+            const int64_t sv = h.sv_s, R = h.R;
+            h.o_psi = take(sizeof(double) * m * sv);
+            h.o_w = take(sizeof(double) * sv * n);
+            h.o_z = take(sizeof(double) * sv * R);
+            h.o_linv = take(sizeof(double) * R * R);
+            h.o_msv = take(sizeof(double) * R * n);
+            h.o_f = take(sizeof(double) * m * R);
+            h.o_ht = take(sizeof(double) * R * R);
+            h.o_cross = take(sizeof(double) * R);
+        }
         if (save) {
             const int64_t mx = std::max(m, n);
             h.o_bw_w[0] = take(sizeof(double) * mx * l);
@@ -636,6 +655,25 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             }
             P.omega = add_idx(B, d, cnt);
         }
+        // single-view plans: the co-range test matrix, stored as Psi^T = the m x s
+        // Gaussian of the seed with its top bit flipped (FP64)
+        if (P.single_view) {
+            std::vector<OmegaDesc> d(np);
+            std::vector<int> cnt(np);
+            for (int b = 0; b < np; ++b) {
+                const ProbHost& h = P.probs[b];
+                OmegaDesc& o = d[b];
+                memset(&o, 0, sizeof(o));
+                o.Om = wsp<char>(P, h.o_psi);
+                o.seed = h.seed ^ (1ull << 63);
+                o.n = (int)h.m;
+                o.l = h.sv_s;
+                o.elem = E_F64;
+                const int64_t pairs = ((h.m + 1) / 2) * (int64_t)h.sv_s;
+                cnt[b] = (int)((pairs + 255) / 256);
+            }
+            P.omega_psi = add_idx(B, d, cnt);
+        }
         const GemmKind gk = P.prec == RSVD_PREC_F64 ? GK_F64 : (P.prec == RSVD_PREC_F32 ? GK_F32 : GK_BF16);
         const Elem ea_sk = P.need_cast ? P.e_sketch : es;
         const int nst = 2 * P.max_q + 1;
@@ -828,6 +866,63 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             }
             P.g_lqx = tgemm(GK_F64, E_F64, E_F64, E_F64, dx);
         }
+        // single-view plans: W = Psi A and Z = Psi Q (FP64), the Cholesky factor L of
+        // Z^T Z, Z <- Z L^-T and L^-T (in place on the identity), M = Z^T W, and the
+        // Jacobi input X = L^-T M = (Z^T Z)^-1 Z^T W = (Psi Q)^+ W
+        if (P.single_view) {
+            std::vector<GemmDesc> dw(np), dz(np), dg(np), dm(np), dx(np);
+            std::vector<QrDesc> dq(np), dqi(np);
+            std::vector<EyeDesc> de(np);
+            std::vector<int> ones(np, 1), rowblk(np), rowblki(np), ce(np);
+            for (int b = 0; b < np; ++b) {
+                const ProbHost& h = P.probs[b];
+                const int R = h.R, sv = h.sv_s;
+                const double* G = wsp<double>(P, h.o_psi);
+                double* W = wsp<double>(P, h.o_w);
+                double* Z = wsp<double>(P, h.o_z);
+                double* Li = wsp<double>(P, h.o_linv);
+                double* M = wsp<double>(P, h.o_msv);
+                int* flag = wsp<int>(P, h.o_flags) + 2 * P.max_q + 1;  // the lq slot (single-view plans have no lq)
+                dw[b] = gd(G, sv, 1, A[b], h.lda, 0, W, h.n, sv, (int)h.n, (int)h.m);
+                dz[b] = gd(G, sv, 1, final_q(P, h), R, 0, Z, R, sv, R, (int)h.m);
+                dg[b] = gd(Z, R, 1, Z, R, 0, wsp<double>(P, h.o_g), R, R, R, sv, flag);
+                dg[b].lower = 1;
+                QrDesc& q = dq[b];
+                memset(&q, 0, sizeof(q));
+                q.Min = Z;
+                q.Qout = Z;
+                q.G = wsp<double>(P, h.o_g);
+                q.L = wsp<double>(P, h.o_lwork);
+                q.D = wsp<double>(P, h.o_dwork);
+                q.flag = flag;
+                q.rows = sv;
+                q.l = R;
+                q.min_elem = E_F64;
+                dqi[b] = q;
+                dqi[b].Min = Li;
+                dqi[b].Qout = Li;
+                dqi[b].rows = R;
+                rowblk[b] = (sv + 15) / 16;
+                rowblki[b] = (R + 15) / 16;
+                EyeDesc& e = de[b];
+                memset(&e, 0, sizeof(e));
+                e.P = Li;
+                e.ldp = R;
+                e.R = R;
+                ce[b] = (int)(((int64_t)R * R + 255) / 256);
+                dm[b] = gd(Z, R, 1, W, h.n, 0, M, h.n, R, (int)h.n, sv, flag);
+                dx[b] = gd(Li, R, 0, M, h.n, 0, wsp<double>(P, h.o_b), h.C, R, (int)h.n, R, flag);
+            }
+            P.g_sv_w = add_gemm(B, GK_F64, E_F64, es, E_F64, dw);
+            P.g_sv_z = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, dz);
+            P.g_sv_gram = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, dg);
+            P.sv_qr = add_idx(B, dq, ones);
+            P.sv_eye = add_idx(B, de, ce);
+            P.sv_trsm_z = add_idx(B, dq, rowblk);
+            P.sv_trsm_i = add_idx(B, dqi, rowblki);
+            P.g_sv_m = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, dm);
+            P.g_sv_x = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, dx);
+        }
         // B = Q^T A in FP64 from the stored A (the other problems)
         {
             std::vector<GemmDesc> d(np);
@@ -922,6 +1017,36 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             P.jac_grid = (int)std::max<int64_t>(1, std::min(ntasks, res));
         }
     }
+    // single-view plans: 2 sigma_i u_i^T A v_i for every Jacobi row i, from
+    // F = A X^T (X the rotated rows, FP64 from the stored A), H^T = F^T Q and
+    // u_i = Q P(i, :)^T: 2 sum_j P(i, j) H^T(i, j)
+    if (P.single_view) {
+        std::vector<GemmDesc> df(np), dh(np);
+        std::vector<RowDotDesc> dr(np);
+        std::vector<int> rows4(np);
+        for (int b = 0; b < np; ++b) {
+            const ProbHost& h = P.probs[b];
+            const int R = h.R;
+            double* F = wsp<double>(P, h.o_f);
+            double* Ht = wsp<double>(P, h.o_ht);
+            df[b] = gd(A[b], h.lda, 0, wsp<double>(P, h.o_b), h.C, 1, F, R, (int)h.m, R, (int)h.n);
+            dh[b] = gd(F, R, 1, final_q(P, h), R, 0, Ht, R, R, R, (int)h.m);
+            RowDotDesc& r = dr[b];
+            memset(&r, 0, sizeof(r));
+            r.X = wsp<double>(P, h.o_p);
+            r.Y = Ht;
+            r.out = wsp<double>(P, h.o_cross);
+            r.ldx = R;
+            r.ldy = R;
+            r.rows = R;
+            r.cols = R;
+            r.alpha = 2.0;
+            rows4[b] = (R + 3) / 4;
+        }
+        P.g_sv_f = add_gemm(B, GK_F64, es, E_F64, E_F64, df);
+        P.g_sv_ht = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, dh);
+        P.sv_cross = add_idx(B, dr, rows4);
+    }
     // finish + sign fix
     {
         std::vector<FinDesc> d(np);
@@ -956,6 +1081,8 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
             f.max_sweeps = P.max_sweeps;
             f.delta = h.delta;
             f.jac_err = P.jac_persistent ? wsp<int>(P, P.off_sched) + 1 : nullptr;
+            f.cross = P.single_view ? wsp<double>(P, h.o_cross) : nullptr;
+            f.sv_flag = P.single_view ? wsp<int>(P, h.o_flags) + 2 * P.max_q + 1 : nullptr;
             rows4[b] = (h.R + 3) / 4;
             vt4[b] = (int)((h.k + 3) / 4);
             utiles[b] = h.mode == 0 ? 0 : (int)(((h.k + 63) / 64) * ((h.m + 63) / 64));
@@ -1196,6 +1323,10 @@ int enqueue(rsvd_plan& P, hipStream_t s)
     if (!P.fullsvd) {
         PLAUNCH(RSVD_PHASE_OMEGA, 0.0,
                 launch_omega(dp<OmegaDesc>(P, P.omega.off_desc), dp<int>(P, P.omega.off_begin), np, P.omega.total, s));
+        if (P.single_view)
+            PLAUNCH(RSVD_PHASE_OMEGA, 0.0,
+                    launch_omega(dp<OmegaDesc>(P, P.omega_psi.off_desc), dp<int>(P, P.omega_psi.off_begin), np,
+                                 P.omega_psi.total, s));
         const int nst = 2 * P.max_q + 1;
         for (int st = 0; st < nst; ++st) {
             if ((rc = gemm(P, P.g_sketch[st], s, RSVD_PHASE_SKETCH)) != RSVD_OK) return rc;
@@ -1221,6 +1352,24 @@ int enqueue(rsvd_plan& P, hipStream_t s)
                 PLAUNCH(RSVD_PHASE_OTHER, 0.0,
                         launch_copy_f64(dp<CopyDesc>(P, P.kcopy[st].off_desc), dp<int>(P, P.kcopy[st].off_begin), np,
                                         P.kcopy[st].total, s));
+        }
+        if (P.single_view) {
+            // the co-range sketch and the Jacobi input X = (Psi Q)^+ W
+            if ((rc = gemm(P, P.g_sv_w, s, RSVD_PHASE_SKETCH)) != RSVD_OK) return rc;
+            if ((rc = gemm(P, P.g_sv_z, s, RSVD_PHASE_PROJECT)) != RSVD_OK) return rc;
+            if ((rc = gemm(P, P.g_sv_gram, s, RSVD_PHASE_GRAM)) != RSVD_OK) return rc;
+            PLAUNCH(RSVD_PHASE_CHOL, 0.0, launch_chol(dp<QrDesc>(P, P.sv_qr.off_desc), np, P.max_l, s));
+            PLAUNCH(RSVD_PHASE_TRSM, 0.0,
+                    launch_trsm(dp<QrDesc>(P, P.sv_trsm_z.off_desc), dp<int>(P, P.sv_trsm_z.off_begin), np,
+                                P.sv_trsm_z.total, 0, E_F64, P.max_l, s));
+            PLAUNCH(RSVD_PHASE_OTHER, 0.0,
+                    launch_eye(dp<EyeDesc>(P, P.sv_eye.off_desc), dp<int>(P, P.sv_eye.off_begin), np, P.sv_eye.total,
+                               s));
+            PLAUNCH(RSVD_PHASE_TRSM, 0.0,
+                    launch_trsm(dp<QrDesc>(P, P.sv_trsm_i.off_desc), dp<int>(P, P.sv_trsm_i.off_begin), np,
+                                P.sv_trsm_i.total, 0, E_F64, P.max_l, s));
+            if ((rc = gemm(P, P.g_sv_m, s, RSVD_PHASE_PROJECT)) != RSVD_OK) return rc;
+            if ((rc = gemm(P, P.g_sv_x, s, RSVD_PHASE_PROJECT)) != RSVD_OK) return rc;
         }
         if (P.krylov) {
             if ((rc = gemm(P, P.g_kgram1, s, RSVD_PHASE_GRAM)) != RSVD_OK) return rc;
@@ -1250,7 +1399,7 @@ int enqueue(rsvd_plan& P, hipStream_t s)
             PLAUNCH(RSVD_PHASE_HOUSEHOLDER, 0.0, householder(P, dp<QrDesc>(P, P.lq_qr[0].off_desc), s));
             if ((rc = gemm(P, P.g_lqx, s, RSVD_PHASE_PROJECT)) != RSVD_OK) return rc;
         }
-        if ((rc = gemm(P, P.g_b, s, RSVD_PHASE_PROJECT)) != RSVD_OK) return rc;
+        if (!P.single_view && (rc = gemm(P, P.g_b, s, RSVD_PHASE_PROJECT)) != RSVD_OK) return rc;
     } else {
         PLAUNCH(RSVD_PHASE_OTHER, 0.0,
                 launch_copy_f64(dp<CopyDesc>(P, P.copy.off_desc), dp<int>(P, P.copy.off_begin), np, P.copy.total, s));
@@ -1268,6 +1417,14 @@ int enqueue(rsvd_plan& P, hipStream_t s)
                 PLAUNCH(RSVD_PHASE_JACOBI, 0.0,
                         launch_jacobi_round(dp<JacDesc>(P, P.jac.off_desc), dp<int>(P, P.jac.off_begin), np,
                                             P.jac.total, sw, r, P.jac_variant, s));
+    }
+    if (P.single_view) {
+        // the true error of each triplet needs u_i^T A v_i: one more product with A
+        if ((rc = gemm(P, P.g_sv_f, s, RSVD_PHASE_FINISH)) != RSVD_OK) return rc;
+        if ((rc = gemm(P, P.g_sv_ht, s, RSVD_PHASE_FINISH)) != RSVD_OK) return rc;
+        PLAUNCH(RSVD_PHASE_FINISH, 0.0,
+                launch_rowdot(dp<RowDotDesc>(P, P.sv_cross.off_desc), dp<int>(P, P.sv_cross.off_begin), np,
+                              P.sv_cross.total, s));
     }
     PLAUNCH(RSVD_PHASE_FINISH, 0.0,
             launch_finish(dp<FinDesc>(P, P.finish.off_desc), np, dp<int>(P, P.fin_norm.off_begin), P.fin_norm.total,
@@ -1585,6 +1742,10 @@ int plan_setup(rsvd_plan* P, const rsvd_problem_t* probs, int64_t batch, rsvd_dt
     const bool krylov = (flags & RSVD_PLAN_BLOCK_KRYLOV) != 0;
     if (krylov && (fullsvd || (flags & RSVD_PLAN_SAVE)))
         return fail(RSVD_ERR_INVALID, "block-Krylov plans are RSVD plans without a saved forward");
+    const bool single_view = (flags & RSVD_PLAN_SINGLE_VIEW) != 0;
+    if (single_view && (fullsvd || krylov || (flags & RSVD_PLAN_SAVE)))
+        return fail(RSVD_ERR_INVALID,
+                    "single-view plans are RSVD plans without a saved forward and without block-Krylov");
     for (int64_t b = 0; b < batch; ++b) {
         int rc = validate_problem(probs[b], fullsvd);
         if (rc != RSVD_OK) return fail(rc, "problem " + std::to_string(b) + ": " + g_err);
@@ -1597,6 +1758,7 @@ int plan_setup(rsvd_plan* P, const rsvd_problem_t* probs, int64_t batch, rsvd_dt
         }
     }
     P->krylov = krylov;
+    P->single_view = single_view;
     P->complex_omega = (flags & PLAN_CPLX_OMEGA) != 0;
     P->nprob = (int)batch;
     P->dt = dt;
@@ -1618,7 +1780,7 @@ int plan_setup(rsvd_plan* P, const rsvd_problem_t* probs, int64_t batch, rsvd_dt
         const int64_t mn = std::min(p.m, p.n);
         h.k = std::min(p.k, mn);
         h.p = fullsvd ? 0 : p.p;
-        h.q = fullsvd ? 0 : p.q;
+        h.q = (fullsvd || single_view) ? 0 : p.q;  // the single-view scheme has no power steps
         h.ldu = p.ldu ? p.ldu : h.k;
         h.ldvt = p.ldvt ? p.ldvt : p.n;
         h.seed = p.seed;
@@ -1633,8 +1795,9 @@ int plan_setup(rsvd_plan* P, const rsvd_problem_t* probs, int64_t batch, rsvd_dt
             h.l = (int)std::min(h.k + p.p, mn);
             // rows of B: the sketch width, or the block-Krylov width min(l (q + 1), m, n)
             h.R = krylov ? (int)std::min<int64_t>((int64_t)h.l * (h.q + 1), mn) : h.l;
-            h.lq = !(flags & RSVD_PLAN_SAVE) &&
+            h.lq = !(flags & RSVD_PLAN_SAVE) && !single_view &&
                    !((flags & RSVD_PLAN_NO_REFINE) && prec != RSVD_PREC_F64) && (double)p.n >= JAC_LQ_MIN_RATIO * h.R;
+            h.sv_s = single_view ? (int)std::min<int64_t>(2 * (int64_t)h.l + 1, p.m) : 0;
             h.C = h.lq ? h.R : (int)p.n;
             h.mode = 0;
         }
@@ -1890,6 +2053,7 @@ int complex_plan_create(const rsvd_problem_t* probs, int64_t batch, rsvd_dtype_t
     if (!probs || batch < 1 || batch > (1 << 20)) return fail(RSVD_ERR_INVALID, "batch must be in [1, 2^20]");
     if (dt != RSVD_F64) return fail(RSVD_ERR_INVALID, "complex plans hold complex double (dtype RSVD_F64)");
     if (flags & RSVD_PLAN_SAVE) return fail(RSVD_ERR_INVALID, "complex plans have no adjoint (RSVD_PLAN_SAVE)");
+    if (flags & RSVD_PLAN_SINGLE_VIEW) return fail(RSVD_ERR_INVALID, "complex plans have no single-view form");
     const bool full = (flags & RSVD_PLAN_FULLSVD) != 0;
     std::vector<rsvd_problem_t> in(batch);
     for (int64_t b = 0; b < batch; ++b) {
@@ -2474,6 +2638,8 @@ int rsvd_plan_postselect(rsvd_plan_t* plan, int64_t chi, int64_t* chi_s, void* s
     g_err.clear();
     if (!plan) return fail(RSVD_ERR_INVALID, "plan is null");
     if (plan->cx) return fail(RSVD_ERR_INVALID, "post-selection is not available for complex plans");
+    if (plan->single_view)
+        return fail(RSVD_ERR_INVALID, "post-selection is not available for single-view plans (w is not sum sigma^2)");
     if (!chi_s) return fail(RSVD_ERR_INVALID, "chi_s is null");
     if (chi < 0) return fail(RSVD_ERR_INVALID, "chi must be >= 0");
     if (!plan->blob_valid) return fail(RSVD_ERR_INVALID, "postselect needs a preceding rsvd_plan_execute");

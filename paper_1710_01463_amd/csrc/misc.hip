@@ -279,4 +279,26 @@ hipError_t launch_eye(const EyeDesc* d, const int* blk_begin, int nprob, int tot
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void rowdot_kernel(const RowDotDesc* __restrict__ descs,
+                                                     const int* __restrict__ blk_begin, int nprob)
+{
+    const int2 wi_ = wg_item(blk_begin, blockIdx.x);
+    const RowDotDesc& d = descs[wi_.x];
+    const int lane = threadIdx.x & 63, i = 4 * wi_.y + (threadIdx.x >> 6);
+    if (i >= d.rows) return;
+    const GLB double* __restrict__ x = to_glb(d.X) + (int64_t)i * d.ldx;
+    const GLB double* __restrict__ y = to_glb(d.Y) + (int64_t)i * d.ldy;
+    double acc = 0.0;
+    for (int j = lane; j < d.cols; j += 64) acc = fma(x[j], y[j], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) to_glb(d.out)[i] = d.alpha * acc;
+}
+
+hipError_t launch_rowdot(const RowDotDesc* d, const int* blk_begin, int nprob, int total_blocks, hipStream_t s)
+{
+    if (total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rowdot_kernel, dim3(total_blocks), dim3(256), 0, s, d, blk_begin, nprob);
+    return hipGetLastError();
+}
+
 }  // namespace rsvd
