@@ -425,6 +425,21 @@ def c4_leg(P, torch, wl, steps, subset_every=16):
            "eps_F_over_delta_EY_median": float(np.median(ratio[opt > 1e-13 * tot])),
            "eps_F_over_delta_EY_max": float(np.max(ratio[opt > 1e-13 * tot])),
            "phases_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1] > 0}}
+    # the tile autotuner on the uneven batch: the first execute of a tuned plan
+    # times every tile of each tunable product on these inputs, then the plan
+    # is timed like the untuned one
+    tplan = P.Plan(plist, torch.float32, "f32", graph=True, tune=True)
+    heur = tplan.tiles()
+    t0 = time.perf_counter()
+    tplan.execute(As)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    tms = timed(torch, lambda: tplan.execute(As), steps)
+    tuned = tplan.tiles()
+    tplan.close()
+    res["tuned"] = {"ms_per_step": tms, "speedup_vs_heuristic": ms / tms, "tuning_execute_s": tune_s,
+                    "products": len(tuned), "changed": int(sum(a != b for a, b in zip(tuned, heur))),
+                    "tiles": [f"{a}x{b}" for a, b in tuned], "heuristic": [f"{a}x{b}" for a, b in heur]}
     sub = list(range(0, len(probs), subset_every))
     Ssub = [As[b] for b in sub]
     splan = P.Plan([plist[b] for b in sub], torch.float32, "f32", graph=True)
@@ -456,12 +471,16 @@ def c4_leg(P, torch, wl, steps, subset_every=16):
 
 
 def krylov_leg(P, torch, wl, steps):
-    """Block-Krylov variant against the RSVD at equal passes over A (same k,
-    p, q, seed): step time and eps_F / delta_EY (delta_EY from the exact
-    spectrum the inputs are built with) on the TTN-shaped batch (16 x 1024^2,
-    BF16 sketch products, L = (k + p)(q + 1) = 320) and the headline batch
-    (32 x 512^2 FP64, where L = min(272 x 3, 512) = 512 spans the whole row
-    space and the projection is exact)."""
+    """The outlook's variants against the RSVD (same k, p, seed): step time and
+    eps_F / delta_EY (delta_EY from the exact spectrum the inputs are built
+    with) on the TTN-shaped batch (16 x 1024^2, BF16 sketch products) and the
+    headline batch (32 x 512^2 FP64).
+    * block-Krylov at equal passes over A (same q): L = (k + p)(q + 1) = 320 on
+      the first batch; on the second L = min(272 x 3, 512) = 512 spans the
+      whole row space and the projection is exact;
+    * single view (Y = A Omega and W = Psi A, no power steps; one more product
+      with A for its true error) against the RSVD without power steps (q = 0,
+      two passes over A: Y and B)."""
     import numpy as np
     out = {}
     for name, W, dtype, prec in (("C3_bf16", wl.c3(16), torch.float32, "bf16"), ("C2_f64", wl.c2(32), torch.float64, "f64")):
@@ -471,8 +490,10 @@ def krylov_leg(P, torch, wl, steps):
         plist = [dict(m=pr.m, n=pr.n, k=pr.k, p=pr.p, q=pr.q, seed=pr.seed) for pr in probs]
         opt = np.array([np.sum(pr.spectrum[pr.k:] ** 2) for pr in probs])
         res = {"L": min(probs[0].l * (probs[0].q + 1), probs[0].m, probs[0].n), "q": probs[0].q}
-        for key, kr in (("rsvd", False), ("krylov", True)):
-            plan = P.Plan(plist, dtype, prec, graph=True, block_krylov=kr)
+        plist0 = [dict(pr, q=0) for pr in plist]
+        for key, pl, kw in (("rsvd", plist, {}), ("krylov", plist, dict(block_krylov=True)),
+                            ("rsvd_q0", plist0, {}), ("single_view", plist0, dict(single_view=True))):
+            plan = P.Plan(pl, dtype, prec, graph=True, **kw)
             ms = timed(torch, lambda: plan.execute(As), steps)
             _, w, _, info = plan.execute(As)
             torch.cuda.synchronize()
@@ -482,6 +503,36 @@ def krylov_leg(P, torch, wl, steps):
             plan.close()
         out[name] = res
         del As
+    return out
+
+
+def complex_leg(P, torch, wl, steps):
+    """The headline shape in complex double (the paper's simulations are
+    complex): 32 x 512^2, A = U diag(i^-1.5) V^H with Haar unitary U, V,
+    k = 256, p = 16, q = 2, one complex plan (the real embedding, 1024^2 and
+    rank 512, on the device), one graph launch per step; eps_F / delta_EY
+    from the exact spectrum."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    probs = wl.c2(32).problems
+    log("[bench] complex leg: generating 32 complex matrices 512x512")
+    with ThreadPoolExecutor(8) as ex:
+        mats = list(ex.map(lambda pr: wl.make_complex_matrix(pr.m, pr.n, pr.spectrum, pr.a_seed), probs))
+    As = [torch.from_numpy(A).cuda() for A in mats]
+    plist = [dict(m=pr.m, n=pr.n, k=pr.k, p=pr.p, q=pr.q, seed=pr.seed) for pr in probs]
+    plan = P.Plan(plist, torch.complex128, "f64", graph=True)
+    ms = timed(torch, lambda: plan.execute(As), steps)
+    _, w, kk, info = plan.execute(As)
+    torch.cuda.synchronize()
+    plan.close()
+    opt = np.array([np.sum(pr.spectrum[pr.k:] ** 2) for pr in probs])
+    w = w.cpu().numpy()
+    out = {"workload": "C2 shape in complex double: 32 x 512x512, s_i=i^-1.5, k=256 p=16 q=2",
+           "ms_per_step": ms, "per_s": len(probs) / (ms / 1e3),
+           "eps_F_over_delta_EY": float(np.mean(np.sqrt(w / opt))),
+           "status_ok": bool(np.all(info.cpu().numpy() == 0))}
+    del As
+    torch.cuda.empty_cache()
     return out
 
 
@@ -733,7 +784,8 @@ def main():
         log("[bench] C1 leg")
         result["c1"] = c1_leg(P, torch, wl, args.c1_reps)
         result["c4"] = c4_leg(P, torch, wl, 3)
-        result["block_krylov"] = krylov_leg(P, torch, wl, 5)
+        result["variants"] = krylov_leg(P, torch, wl, 5)
+        result["complex"] = complex_leg(P, torch, wl, 3)
         result["bandwidth"] = bandwidth_leg(torch)
 
     if not args.no_compare and args.prec == "f64":
