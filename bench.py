@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-diff", action="store_true", help="skip the forward + adjoint leg")
     ap.add_argument("--diff-batch", type=int, default=64)
     ap.add_argument("--diff-steps", type=int, default=5)
+    ap.add_argument("--only", choices=["c4"], default=None,
+                    help="run one leg alone and print its JSON (for profiling that leg's kernels)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -391,7 +393,7 @@ def c2_f32_leg(P, torch, probs, mats, w_full, sig64, steps):
     return res
 
 
-def c4_leg(P, torch, wl, steps, subset_every=16):
+def c4_leg(P, torch, wl, steps, subset_every=16, extras=True):
     """The uneven batch of symmetry sectors: 512 problems, m, n uniform in
     [32, 2048], s_i = exp(-alpha i), k = min(m, n)/4 rounded to 8, p = 16,
     q = 2, delta_trunc = 1e-10, stored FP32 with FP32 sketch products; one
@@ -425,6 +427,10 @@ def c4_leg(P, torch, wl, steps, subset_every=16):
            "eps_F_over_delta_EY_median": float(np.median(ratio[opt > 1e-13 * tot])),
            "eps_F_over_delta_EY_max": float(np.max(ratio[opt > 1e-13 * tot])),
            "phases_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1] > 0}}
+    if not extras:  # the batch plan alone (profiling)
+        del As
+        torch.cuda.empty_cache()
+        return res
     # the tile autotuner on the uneven batch: the first execute of a tuned plan
     # times every tile of each tunable product on these inputs, then the plan
     # is timed like the untuned one
@@ -609,6 +615,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n, "copies": 3}))
+        return
+    if args.only == "c4":
+        print(json.dumps(c4_leg(P, torch, wl, args.steps, extras=False)))
         return
     W = wl.c2(args.batch)
     probs = W.problems
