@@ -122,6 +122,8 @@ struct ProbHost {
     size_t o_psi = 0, o_w = 0, o_z = 0, o_linv = 0, o_msv = 0, o_f = 0, o_ht = 0, o_cross = 0;
     // reverse pass (RSVD_PLAN_SAVE only)
     size_t o_bw_w[2], o_bw_vbt, o_bw_vts, o_bw_bb, o_bw_ut, o_bw_utb, o_bw_eu, o_bw_ev, o_bw_kp, o_bw_sb;
+    // dA = Lcat Rcat^T: the 2q + 2 terms L_t R_t^T of the reverse pass side by side (m x (2q + 2) l, n x (2q + 2) l)
+    size_t o_bw_lcat, o_bw_rcat;
     int nchunks;
 };
 
@@ -252,8 +254,9 @@ struct rsvd_plan {
     bool tuner = false;  // the eager execute under way times the candidate tiles
     bool tuned = false;
     struct BwStage {
-        GemmLaunch c, qs, r, da, qprev;
+        GemmLaunch c, qs, r, qprev;
         IdxLaunch sym, tri, trsm;
+        IdxLaunch cat_l, cat_r;  // the stage's dA term L R^T copied into its slices of Lcat, Rcat
     };
     struct Backward {
         Blob hb;
@@ -268,7 +271,9 @@ struct rsvd_plan {
         std::vector<void*> ldA;
         double broad = 0.0;
         IdxLaunch prep, core;
-        GemmLaunch utb, qb0, eu, ev, nn, bb, qba, da0;
+        GemmLaunch utb, qb0, eu, ev, nn, bb, qba;
+        IdxLaunch cat_l0, cat_r0;  // the head's dA term Q Bbar into slice 0
+        GemmLaunch da;             // dA = Lcat Rcat^T, every term in one product
         std::vector<BwStage> st;  // indexed by stage
         hipGraph_t graph = nullptr;
         hipGraphExec_t gexec = nullptr;
@@ -388,6 +393,9 @@ void layout(rsvd_plan& P)
             h.o_bw_ev = take(sizeof(double) * l * l);
             h.o_bw_kp = take(sizeof(double) * l * l);
             h.o_bw_sb = take(sizeof(double) * l);
+            const int64_t tl = (2 * h.q + 2) * l;
+            h.o_bw_lcat = take(sizeof(double) * m * tl);
+            h.o_bw_rcat = take(sizeof(double) * n * tl);
         }
     }
     // flags: per problem (2 q_max + 1) QR flags followed by max_sweeps rot flags
@@ -1448,6 +1456,26 @@ int enqueue(rsvd_plan& P, hipStream_t s)
 // the power iteration, and every product that involves A adds its share of
 // dA.  The two (max(m, n) x l) work buffers alternate between Qbar and the
 // next stage's Qbar; the triangular solve works in place.
+// Copy of the rows x cols matrix A (element elem, leading dimension lda) into
+// X (leading dimension ldx), transposed when asked; *count receives its
+// 64 x 64 tiles.
+CopyDesc copy_desc(const void* A, Elem elem, int rows, int cols, int64_t lda, double* X, int64_t ldx, bool transpose,
+                   int* count)
+{
+    CopyDesc c;
+    memset(&c, 0, sizeof(c));
+    c.A = A;
+    c.X = X;
+    c.lda = lda;
+    c.ldx = ldx;
+    c.m = rows;
+    c.n = cols;
+    c.a_elem = elem;
+    c.transpose = transpose ? 1 : 0;
+    *count = ((rows + 63) / 64) * ((cols + 63) / 64);
+    return c;
+}
+
 void build_bw_blob(rsvd_plan& P, const void* const* dU, const void* const* dS, const void* const* dVT,
                    void* const* dA, double broad)
 {
@@ -1496,7 +1524,9 @@ void build_bw_blob(rsvd_plan& P, const void* const* dU, const void* const* dS, c
     W.prep = add_idx(B, bd, cprep);
     W.core = add_idx(B, bd, ccore);
     {
-        std::vector<GemmDesc> utb(np), qb0(np), eu(np), ev(np), nn(np), bb(np), qba(np), da0(np);
+        std::vector<GemmDesc> utb(np), qb0(np), eu(np), ev(np), nn(np), bb(np), qba(np), dac(np);
+        std::vector<CopyDesc> cl0(np), cr0(np);
+        std::vector<int> ccl0(np), ccr0(np);
         for (int b = 0; b < np; ++b) {
             const ProbHost& h = P.probs[b];
             const int l = h.l, m = (int)h.m, n = (int)h.n;
@@ -1518,10 +1548,15 @@ void build_bw_blob(rsvd_plan& P, const void* const* dU, const void* const* dS, c
             nn[b] = gd(wsp<double>(P, h.o_bw_kp), l, 0, Vts, n, 0, Vbt, n, l, n, l);
             nn[b].accumulate = 1;
             bb[b] = gd(Ut, l, 0, Vbt, n, 0, Bb, n, l, n, l);
-            // B = Q^T A:  Qbar += A Bbar^T,  dA = Q Bbar
+            // B = Q^T A:  Qbar += A Bbar^T;  dA's term Q Bbar goes into slice 0 (L = Q, R = Bbar^T)
             qba[b] = gd(P.lastA[b], h.lda, 0, Bb, n, 1, W0, l, m, l, n);
             qba[b].accumulate = 1;
-            da0[b] = gd(Qf, l, 0, Bb, n, 0, dA[b], h.lda, m, n, l);
+            const int64_t tl = (2 * h.q + 2) * l;
+            double* Lc = wsp<double>(P, h.o_bw_lcat);
+            double* Rc = wsp<double>(P, h.o_bw_rcat);
+            cl0[b] = copy_desc(Qf, E_F64, m, l, l, Lc, tl, false, &ccl0[b]);
+            cr0[b] = copy_desc(Bb, E_F64, l, n, n, Rc, tl, true, &ccr0[b]);  // Bbar (l x n) transposed
+            dac[b] = gd(Lc, tl, 0, Rc, tl, 1, dA[b], h.lda, m, n, (int)tl);
         }
         W.utb = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, utb);
         W.qb0 = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, qb0);
@@ -1530,15 +1565,22 @@ void build_bw_blob(rsvd_plan& P, const void* const* dU, const void* const* dS, c
         W.nn = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, nn);
         W.bb = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, bb);
         W.qba = add_gemm(B, GK_F64, es, E_F64, E_F64, qba);
-        W.da0 = add_gemm(B, GK_F64, E_F64, E_F64, es, da0);
+        W.cat_l0 = add_idx(B, cl0, ccl0);
+        W.cat_r0 = add_idx(B, cr0, ccr0);
+        W.da = add_gemm(B, GK_F64, E_F64, E_F64, es, dac);
     }
     const int nst = 2 * P.max_q + 1;
     W.st.assign(nst, rsvd_plan::BwStage());
     for (int s = nst - 1; s >= 0; --s) {
-        std::vector<GemmDesc> c(np, none), qs(np, none), r(np, none), da(np, none), qprev(np, none);
+        std::vector<GemmDesc> c(np, none), qs(np, none), r(np, none), qprev(np, none);
         std::vector<BwDesc> sym(bd);
         std::vector<QrDesc> tri(np);
-        std::vector<int> csym(np, 0), ctri(np, 1), ctrsm(np, 0);
+        std::vector<int> csym(np, 0), ctri(np, 1), ctrsm(np, 0), ccl(np, 0), ccr(np, 0);
+        std::vector<CopyDesc> cl(np), cr(np);
+        for (int b = 0; b < np; ++b) {
+            memset(&cl[b], 0, sizeof(CopyDesc));
+            memset(&cr[b], 0, sizeof(CopyDesc));
+        }
         for (int b = 0; b < np; ++b) {
             const ProbHost& h = P.probs[b];
             memset(&tri[b], 0, sizeof(QrDesc));
@@ -1566,18 +1608,22 @@ void build_bw_blob(rsvd_plan& P, const void* const* dU, const void* const* dS, c
             tri[b].D = wsp<double>(P, h.o_dwork);
             tri[b].rows = rows;
             ctrsm[b] = (rows + 15) / 16;
-            // the product that formed M_s
+            // the product that formed M_s; its dA term L R^T goes into slice 1 + 2q - s
+            const int64_t tl = (2 * h.q + 2) * l, off = (int64_t)(1 + 2 * h.q - s) * l;
+            double* Lc = wsp<double>(P, h.o_bw_lcat) + off;
+            double* Rc = wsp<double>(P, h.o_bw_rcat) + off;
             if (s % 2 == 0) {
                 // M_s = A X_s, X_s = Omega (s = 0) or the previous basis: dA += Mbar X_s^T, Qbar_prev = A^T Mbar
                 const void* Xs = (s == 0) ? (const void*)wsp<char>(P, h.o_om) : wsp<double>(P, h.o_qstage[s - 1]);
-                da[b] = gd(Qb, l, 0, Xs, l, 1, dA[b], h.lda, m, n, l);
+                cl[b] = copy_desc(Qb, E_F64, m, l, l, Lc, tl, false, &ccl[b]);
+                cr[b] = copy_desc(Xs, s == 0 ? P.e_sketch : E_F64, n, l, l, Rc, tl, false, &ccr[b]);
                 if (s > 0) qprev[b] = gd(P.lastA[b], h.lda, 1, Qb, l, 0, Qn, l, n, l, m);
             } else {
                 // M_s = A^T Q_{s-1}: dA += Q_{s-1} Mbar^T, Qbar_prev = A Mbar
-                da[b] = gd(wsp<double>(P, h.o_qstage[s - 1]), l, 0, Qb, l, 1, dA[b], h.lda, m, n, l);
+                cl[b] = copy_desc(wsp<double>(P, h.o_qstage[s - 1]), E_F64, m, l, l, Lc, tl, false, &ccl[b]);
+                cr[b] = copy_desc(Qb, E_F64, n, l, l, Rc, tl, false, &ccr[b]);
                 qprev[b] = gd(P.lastA[b], h.lda, 0, Qb, l, 0, Qn, l, m, l, n);
             }
-            da[b].accumulate = 1;
         }
         rsvd_plan::BwStage& st = W.st[s];
         st.c = add_gemm(B, GK_F64, E_F64, E_F64, E_F64, c);
@@ -1586,7 +1632,8 @@ void build_bw_blob(rsvd_plan& P, const void* const* dU, const void* const* dS, c
         st.r = add_gemm(B, GK_F64, E_F64, P.e_y, E_F64, r);
         st.tri = add_idx(B, tri, ctri);
         st.trsm = add_idx(B, tri, ctrsm);
-        st.da = add_gemm(B, GK_F64, E_F64, (s == 0) ? P.e_sketch : E_F64, es, da);
+        st.cat_l = add_idx(B, cl, ccl);
+        st.cat_r = add_idx(B, cr, ccr);
         st.qprev = add_gemm(B, GK_F64, es, E_F64, E_F64, qprev);
     }
     W.hb = std::move(B);
@@ -1614,8 +1661,15 @@ int enqueue_backward(rsvd_plan& P, hipStream_t s)
         if ((rc = bgemm(*g)) != RSVD_OK) return rc;
     PLAUNCH(RSVD_PHASE_BW_SMALL, 0.0,
             launch_bw_core((const BwDesc*)dd(W.core.off_desc), (const int*)dd(W.core.off_begin), np, W.core.total, s));
-    for (const GemmLaunch* g : {&W.nn, &W.bb, &W.qba, &W.da0})
+    auto bcopy = [&](const IdxLaunch& c) -> int {
+        if (c.total <= 0) return RSVD_OK;
+        PLAUNCH(RSVD_PHASE_BW_SMALL, 0.0,
+                launch_copy_f64((const CopyDesc*)dd(c.off_desc), (const int*)dd(c.off_begin), np, c.total, s));
+        return RSVD_OK;
+    };
+    for (const GemmLaunch* g : {&W.nn, &W.bb, &W.qba})
         if ((rc = bgemm(*g)) != RSVD_OK) return rc;
+    if ((rc = bcopy(W.cat_l0)) != RSVD_OK || (rc = bcopy(W.cat_r0)) != RSVD_OK) return rc;
     for (int st = (int)W.st.size() - 1; st >= 0; --st) {
         const rsvd_plan::BwStage& S = W.st[st];
         if ((rc = bgemm(S.c)) != RSVD_OK) return rc;
@@ -1627,10 +1681,11 @@ int enqueue_backward(rsvd_plan& P, hipStream_t s)
         PLAUNCH(RSVD_PHASE_BW_SMALL, 0.0,
                 launch_trsm_upper((const QrDesc*)dd(S.trsm.off_desc), (const int*)dd(S.trsm.off_begin), np,
                                   S.trsm.total, P.max_l, s));
-        if ((rc = bgemm(S.da)) != RSVD_OK) return rc;
+        if ((rc = bcopy(S.cat_l)) != RSVD_OK || (rc = bcopy(S.cat_r)) != RSVD_OK) return rc;
         if ((rc = bgemm(S.qprev)) != RSVD_OK) return rc;
     }
-    return RSVD_OK;
+    // dA = sum of the 2q + 2 terms L_t R_t^T as one product with inner dimension (2q + 2) l
+    return bgemm(W.da);
 }
 
 int plan_backward(rsvd_plan* P, const void* const* dU, const void* const* dS, const void* const* dVT,
