@@ -197,7 +197,8 @@ def precision_leg(args, P, torch, wl):
     in FP32, s_i = |i^-1.2 (1 + 0.05 xi)|, k = 64, p = 16, q = 3.  The same
     batch runs with BF16 and with FP32 sketch and power-iteration products
     (FP64 Cholesky QR, FP64 projection B = Q^T A, FP64 small SVD) and fully in
-    FP64 (the FP32 values upcast).  Reports the step times, the GEMM work
+    FP64 (the FP32 values upcast), and the two mixed forms again with their last
+    power step in FP64 (RSVD_PLAN_FP64_FINAL).  Reports the step times, the GEMM work
     rate, the truncation error against the optimum and each mixed form's
     singular values against the FP64 path's, relative to sigma_1."""
     import numpy as np
@@ -215,8 +216,12 @@ def precision_leg(args, P, torch, wl):
     out = {"workload": f"C3: {len(probs)} x 1024x1024 FP32 storage, s_i=|i^-1.2 (1+0.05 xi)|, k=64 p=16 q=3"}
     sig = {}
     ref0 = mats[0].astype(np.float64)
-    for prec, dtype, As in (("bf16", torch.float32, A32), ("f32", torch.float32, A32), ("f64", torch.float64, A64)):
-        plan = P.Plan(plist, dtype, prec, graph=True)
+    forms = (("bf16", "bf16", torch.float32, A32, False), ("f32", "f32", torch.float32, A32, False),
+             ("f64", "f64", torch.float64, A64, False), ("bf16_fp64_final", "bf16", torch.float32, A32, True),
+             ("f32_fp64_final", "f32", torch.float32, A32, True))
+    for key, prec_, dtype, As, f64f in forms:
+        prec = key
+        plan = P.Plan(plist, dtype, prec_, graph=True, fp64_final=f64f)
         plan.execute(As)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -236,31 +241,35 @@ def precision_leg(args, P, torch, wl):
         # achieved bytes per second of those passes, against HBM and the cache
         prof = plan.profile(As)
         sk_ms = prof["sketch"][0]
-        nbytes = sum(sketch_bytes(pr, prec) for pr in probs)
+        nbytes = sum(sketch_bytes(pr, prec_, f64f, 8 if dtype == torch.float64 else 4) for pr in probs)
         out[prec]["sketch_ms"] = sk_ms
         out[prec]["sketch_bytes"] = nbytes
-        out[prec]["sketch_GBs"] = nbytes / (sk_ms * 1e-3) / 1e9 if sk_ms else None
-        out[prec]["sketch_frac_of_hbm"] = out[prec]["sketch_GBs"] / 8000.0 if sk_ms else None
+        out[prec]["sketch_GBs"] = nbytes / (sk_ms * 1e-3) / 1e9 if sk_ms and nbytes else None
+        out[prec]["sketch_frac_of_hbm"] = out[prec]["sketch_GBs"] / 8000.0 if out[prec]["sketch_GBs"] else None
         plan.close()
-    for prec in ("bf16", "f32"):
+    for prec in ("bf16", "f32", "bf16_fp64_final", "f32_fp64_final"):
         out[prec]["max_dsigma_over_s1_vs_f64"] = max(
             float(np.max(np.abs(a - b)) / b[0]) for a, b in zip(sig[prec], sig["f64"]))
         out[prec]["speedup_vs_f64"] = out["f64"]["ms"] / out[prec]["ms"]
     return out
 
 
-def sketch_bytes(pr, prec):
+def sketch_bytes(pr, prec, fp64_final=False, storage=4):
     """Algorithmic bytes of the 2q + 1 sketch and power products of one
     problem: each reads A once (sketch precision: 2, 4 or 8 bytes), reads its
     l-column operand (Omega in the sketch precision, the FP64 bases after)
-    and writes its l-column product (FP32 in the mixed modes, else FP64)."""
+    and writes its l-column product (FP32 in the mixed modes, else FP64).
+    With the last power step in FP64 (products 2q - 1 and 2q), those two read
+    A in its storage type (`storage` bytes) and write FP64 products."""
     ea = {"bf16": 2, "f32": 4, "f64": 8}[prec]
     ey = 8 if prec == "f64" else 4
     m, n, l = pr.m, pr.n, pr.l
     total = 0
     for s in range(2 * pr.q + 1):
         rows_in, rows_out = (n, m) if s % 2 == 0 else (m, n)
-        total += m * n * ea + rows_in * l * (ea if s == 0 else 8) + rows_out * l * ey
+        f64 = fp64_final and s >= 2 * pr.q - 1
+        total += (m * n * (storage if f64 else ea) + rows_in * l * (ea if s == 0 else 8)
+                  + rows_out * l * (8 if f64 else ey))
     return total
 
 

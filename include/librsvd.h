@@ -261,6 +261,19 @@ typedef struct rsvd_plan rsvd_plan_t;
  * breaks down.  Not with RSVD_PLAN_FULLSVD, RSVD_PLAN_SAVE,
  * RSVD_PLAN_BLOCK_KRYLOV, RSVD_PLAN_COMPLEX or rsvd_plan_postselect. */
 #define RSVD_PLAN_SINGLE_VIEW 512u
+/* FP64 final power step for mixed-precision plans (RSVD_PREC_F32 or
+ * RSVD_PREC_BF16): the last power iteration, W = A^T Q and Y = A Z with their
+ * orthonormalisations, runs in FP64 from the stored A, so only the earlier
+ * steps use the sketch precision.  The range basis then carries the sketch
+ * precision's rounding only through what the last FP64 step does not damp:
+ * about a factor (sigma_{l+1} / sigma_k)^2 less on decaying spectra, nothing
+ * on nearly flat ones.  The singular values of FP32-output plans sit at
+ * their own FP32 rounding either way (the sketch rounding reaches them only
+ * through incoherent sums, far below an FP32 ulp), so there the option moves
+ * the bases only.  Every problem of the plan must have the same q >= 1.
+ * Not with RSVD_PLAN_SAVE, RSVD_PLAN_BLOCK_KRYLOV, RSVD_PLAN_SINGLE_VIEW or
+ * RSVD_PLAN_FULLSVD; no effect on FP64 plans. */
+#define RSVD_PLAN_FP64_FINAL 1024u
 
 /* Validates the problems, sizes and allocates the plan's device workspace.
  * Returns RSVD_ERR_INVALID for bad problem descriptions. */

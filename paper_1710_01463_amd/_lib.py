@@ -14,7 +14,7 @@ RSVD_ERR_SINGULAR = -6
 RSVD_F64, RSVD_F32 = 0, 1
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 PLAN_FULLSVD, PLAN_GRAPH, PLAN_SAVE, PLAN_NO_REFINE, PLAN_TUNE, PLAN_ROUND_LAUNCHES = 1, 2, 4, 8, 16, 32
-PLAN_BLOCK_KRYLOV, PLAN_COMPLEX, PLAN_BLOCKED_QR, PLAN_SINGLE_VIEW = 64, 128, 256, 512
+PLAN_BLOCK_KRYLOV, PLAN_COMPLEX, PLAN_BLOCKED_QR, PLAN_SINGLE_VIEW, PLAN_FP64_FINAL = 64, 128, 256, 512, 1024
 
 PHASES = ["stage", "omega", "sketch", "gram", "chol", "trsm", "householder", "project", "jacobi",
           "finish", "backproj", "signfix", "other", "bw_gemm", "bw_small"]

@@ -202,6 +202,7 @@ struct rsvd_plan {
     GemmLaunch g_kgram1, g_kgram2;
     IdxLaunch k_qr[2], k_trsm[2];
     bool single_view = false;     // single-view variant (RSVD_PLAN_SINGLE_VIEW)
+    int fp64_from = 1 << 30;      // RSVD_PLAN_FP64_FINAL: the first stage whose products are FP64
     IdxLaunch omega_psi, sv_qr, sv_trsm_z, sv_trsm_i, sv_eye, sv_cross;
     GemmLaunch g_sv_w, g_sv_z, g_sv_gram, g_sv_m, g_sv_x, g_sv_f, g_sv_ht;
     bool hh_blocked = false;      // the Householder fallback runs in blocked form
@@ -342,8 +343,10 @@ void layout(rsvd_plan& P)
         h.o_lwork = take(sizeof(double) * lw * lw);
         h.o_dwork = take(sizeof(double) * ((lw + 15) / 16) * 256);
         if (!save) {
-            shared_m[0] = take((size_t)elem_bytes(P.e_y) * m * l);
-            shared_m[1] = take((size_t)elem_bytes(P.e_y) * n * l);
+            // FP64 final power step: the shared buffers also hold FP64 products
+            const size_t ey = P.fp64_from <= 2 * P.max_q ? sizeof(double) : (size_t)elem_bytes(P.e_y);
+            shared_m[0] = take(ey * m * l);
+            shared_m[1] = take(ey * n * l);
             shared_q[0] = take(sizeof(double) * m * l);
             shared_q[1] = take(sizeof(double) * n * l);
             sl1 = take(sizeof(double) * l * l);
@@ -415,6 +418,10 @@ void layout(rsvd_plan& P)
 }
 
 template <typename T> T* wsp(const rsvd_plan& P, size_t off) { return (T*)(P.ws + off); }
+
+// Element of a stage's product M (the sketch precision's, or FP64 for the
+// stages of an FP64 final power step).
+Elem stage_y(const rsvd_plan& P, int s) { return s >= P.fp64_from ? E_F64 : P.e_y; }
 
 int tiles_of(int M, int N, GemmTile t)
 {
@@ -708,8 +715,10 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
                 dq2[b] = dq[b];
                 dsk[b] = dg1[b] = dg2[b] = none;
                 if (!active) continue;
-                const void* Aop = P.need_cast ? (const void*)wsp<char>(P, h.o_acast) : A[b];
-                const int64_t lda_op = P.need_cast ? h.n : h.lda;
+                // the FP64 stages read the stored A, the others the sketch precision's copy
+                const bool cast = P.need_cast && s < P.fp64_from;
+                const void* Aop = cast ? (const void*)wsp<char>(P, h.o_acast) : A[b];
+                const int64_t lda_op = cast ? h.n : h.lda;
                 void* M = wsp<char>(P, h.o_mstage[s]);
                 double* Qs = wsp<double>(P, h.o_qstage[s]);
                 int* flag = wsp<int>(P, h.o_flags) + s;
@@ -735,7 +744,7 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
                 q.D = wsp<double>(P, h.o_dwork);
                 q.flag = flag;
                 q.rows = (int)rows;
-                q.min_elem = P.e_y;
+                q.min_elem = stage_y(P, s);
                 rowblk[b] = (int)((rows + 15) / 16);
                 // pass 2 (final basis only), in place: G = Q^T Q, Q = Q L2^-T
                 if (final_stage) {
@@ -746,8 +755,11 @@ void build_blob(rsvd_plan& P, const void* const* A, void* const* U, void* const*
                 }
             }
             // X operand element of the sketch GEMMs: Omega at s = 0, FP64 bases afterwards
-            P.g_sketch.push_back(tgemm(gk, ea_sk, s == 0 ? P.e_sketch : E_F64, P.e_y, dsk));
-            P.g_gram1.push_back(add_gemm(B, GK_F64, P.e_y, P.e_y, E_F64, dg1));
+            if (s >= P.fp64_from)
+                P.g_sketch.push_back(tgemm(GK_F64, es, E_F64, E_F64, dsk));
+            else
+                P.g_sketch.push_back(tgemm(gk, ea_sk, s == 0 ? P.e_sketch : E_F64, P.e_y, dsk));
+            P.g_gram1.push_back(add_gemm(B, GK_F64, stage_y(P, s), stage_y(P, s), E_F64, dg1));
             P.g_gram2.push_back(add_gemm(B, GK_F64, E_F64, E_F64, E_F64, dg2));
             std::vector<int> ones(np, 1);
             P.qr.push_back(add_idx(B, dq, ones));
@@ -1346,7 +1358,8 @@ int enqueue(rsvd_plan& P, hipStream_t s)
             if ((rc = gemm(P, P.g_gram1[st], s, RSVD_PHASE_GRAM)) != RSVD_OK) return rc;
             PLAUNCH(RSVD_PHASE_CHOL, 0.0, launch_chol(dp<QrDesc>(P, q1.off_desc), np, P.max_l, s));
             PLAUNCH(RSVD_PHASE_TRSM, 0.0,
-                    launch_trsm(dp<QrDesc>(P, t1.off_desc), dp<int>(P, t1.off_begin), np, t1.total, 1, P.e_y, P.max_l, s));
+                    launch_trsm(dp<QrDesc>(P, t1.off_desc), dp<int>(P, t1.off_begin), np, t1.total, 1, stage_y(P, st),
+                                P.max_l, s));
             // pass 2 for the problems whose final basis this is
             if (t2.total > 0) {
                 if ((rc = gemm(P, P.g_gram2[st], s, RSVD_PHASE_GRAM)) != RSVD_OK) return rc;
@@ -1798,6 +1811,15 @@ int plan_setup(rsvd_plan* P, const rsvd_problem_t* probs, int64_t batch, rsvd_dt
     if (krylov && (fullsvd || (flags & RSVD_PLAN_SAVE)))
         return fail(RSVD_ERR_INVALID, "block-Krylov plans are RSVD plans without a saved forward");
     const bool single_view = (flags & RSVD_PLAN_SINGLE_VIEW) != 0;
+    const bool fp64_final = (flags & RSVD_PLAN_FP64_FINAL) != 0 && prec != RSVD_PREC_F64 && !fullsvd;
+    if (fp64_final) {
+        if (krylov || single_view || (flags & RSVD_PLAN_SAVE))
+            return fail(RSVD_ERR_INVALID,
+                        "the FP64 final power step is not available with block-Krylov, single-view or saving plans");
+        for (int64_t b = 0; b < batch; ++b)
+            if (probs[b].q < 1 || probs[b].q != probs[0].q)
+                return fail(RSVD_ERR_INVALID, "the FP64 final power step needs the same q >= 1 for every problem");
+    }
     if (single_view && (fullsvd || krylov || (flags & RSVD_PLAN_SAVE)))
         return fail(RSVD_ERR_INVALID,
                     "single-view plans are RSVD plans without a saved forward and without block-Krylov");
@@ -1814,6 +1836,7 @@ int plan_setup(rsvd_plan* P, const rsvd_problem_t* probs, int64_t batch, rsvd_dt
     }
     P->krylov = krylov;
     P->single_view = single_view;
+    if (fp64_final) P->fp64_from = (int)(2 * probs[0].q - 1);
     P->complex_omega = (flags & PLAN_CPLX_OMEGA) != 0;
     P->nprob = (int)batch;
     P->dt = dt;

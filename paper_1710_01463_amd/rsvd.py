@@ -141,7 +141,7 @@ class Plan:
 
     def __init__(self, problems, dtype=torch.float64, prec="f64", fullsvd=False, graph=True,
                  save=False, refine=True, tune=False, round_launches=False, block_krylov=False, blocked_qr=False,
-                 single_view=False, device="cuda"):
+                 single_view=False, fp64_final=False, device="cuda"):
         self.dtype = dtype
         self.device = torch.device(device)
         self.fullsvd = fullsvd
@@ -163,7 +163,7 @@ class Plan:
                 (L.PLAN_SAVE if save else 0) | (0 if refine else L.PLAN_NO_REFINE) | \
                 (L.PLAN_TUNE if tune else 0) | (L.PLAN_ROUND_LAUNCHES if round_launches else 0) | \
                 (L.PLAN_BLOCK_KRYLOV if block_krylov else 0) | (L.PLAN_BLOCKED_QR if blocked_qr else 0) | \
-                (L.PLAN_SINGLE_VIEW if single_view else 0) | \
+                (L.PLAN_SINGLE_VIEW if single_view else 0) | (L.PLAN_FP64_FINAL if fp64_final else 0) | \
                 (L.PLAN_COMPLEX if dtype == torch.complex128 else 0)
         h = ctypes.c_void_p()
         L.check(L.lib().rsvd_plan_create(arr, n, _DT[dtype], L.PREC[prec], flags, ctypes.byref(h)))

@@ -164,3 +164,56 @@ def test_householder_fallback_on_steep_spectrum(lib):
     kept = ref.k_kept
     assert np.all(np.abs(S[:kept] - ref.S[:kept]) <= np.maximum(1e-10 * ref.S[:kept], 1e-15 * ref.S[0]))
     assert np.linalg.norm(U[:, :kept].T @ U[:, :kept] - np.eye(kept)) < 1e-12
+
+
+def test_fp64_final_power_step(lib):
+    """RSVD_PLAN_FP64_FINAL: the last power step (A^T Q, A Z and their Cholesky
+    QRs) in FP64 from the stored A.  Bars from the first-order model of the
+    mixed-precision error (written before this test was first run): each FP64
+    power step shrinks the sketch precision's subspace error by about
+    (sigma_{l+1} / sigma_k)^2, so on the BF16 noisy power law (C3-like, k = 32,
+    p = 16, q = 3) the error must not grow (the model predicts about half), and
+    on the nearly flat exponential spectra of the uneven FP32 batch it stays
+    within 2 u32 sigma_1 (the FP32 outputs' own rounding plus the sketch term).  FP64 plans ignore
+    the flag; plans with differing q, or q = 0, are rejected."""
+    s = wl.spectrum_noisy_power(384, 1.2, 0.05, 11)
+    mats, probs = zip(*[case(384, 384, 32, 16, 3, s, 400 + b) for b in range(2)])
+    plain, _, _, info_p = run_plan(lib, mats, probs, torch.float32, "bf16")
+    plan = lib.Plan(probs, torch.float32, "bf16", fp64_final=True)
+    outs, w, kk, info = plan.execute([torch.from_numpy(np.ascontiguousarray(A)).cuda() for A in mats])
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0) and np.all(info_p == 0)
+    for (Up, Sp, VTp), o, A, pr in zip(plain, outs, mats, probs):
+        ref = oracle.rsvd(A.astype(np.float64), pr["k"], pr["p"], pr["q"], pr["seed"])
+        e_plain = np.max(np.abs(Sp - ref.S)) / ref.S[0]
+        e_final = np.max(np.abs(o[1].double().cpu().numpy() - ref.S)) / ref.S[0]
+        print(f"BF16 max|dS|/s1: {e_plain:.2e} plain, {e_final:.2e} with the FP64 final power step")
+        assert e_final <= 1.05 * e_plain and e_final <= 2e-5
+    plan.close()
+    mats, probs = c4_like(12, 4, 320)
+    probs = [dict(pr, q=2) for pr in probs]
+    res, w, kk, info = run_plan(lib, mats, probs, torch.float32, "f32")
+    plan = lib.Plan(probs, torch.float32, "f32", fp64_final=True)
+    outs, w2, kk2, info2 = plan.execute([torch.from_numpy(np.ascontiguousarray(A)).cuda() for A in mats])
+    torch.cuda.synchronize()
+    assert np.all(info2.cpu().numpy() == 0)
+    kk2 = kk2.cpu().numpy()
+    for i, (o, A, pr) in enumerate(zip(outs, mats, probs)):
+        A64 = A.astype(np.float64)
+        ref = oracle.rsvd(A64, pr["k"], pr["p"], pr["q"], pr["seed"], pr["delta"])
+        if kk2[i] != ref.k_kept:
+            assert abs(ref.w / np.sum(A64 ** 2) - 1e-10) < 1e-11
+            continue
+        S = o[1].double().cpu().numpy()
+        kept = ref.k_kept
+        e_final = np.max(np.abs(S[:kept] - ref.S[:kept])) / ref.S[0]
+        e_plain = np.max(np.abs(res[i][1][:kept] - ref.S[:kept])) / ref.S[0]
+        print(f"FP32 flat problem {i}: {e_plain:.2e} plain, {e_final:.2e} with the FP64 final power step")
+        assert e_final <= 2 * 2.0 ** -24
+    plan.close()
+    # rejected forms
+    with pytest.raises(RuntimeError):
+        lib.Plan([dict(m=64, n=64, k=8, p=4, q=0, seed=1)], torch.float32, "f32", fp64_final=True)
+    with pytest.raises(RuntimeError):
+        lib.Plan([dict(m=64, n=64, k=8, p=4, q=1, seed=1), dict(m=64, n=64, k=8, p=4, q=2, seed=2)],
+                 torch.float32, "f32", fp64_final=True)
