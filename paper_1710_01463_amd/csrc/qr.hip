@@ -11,6 +11,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace rsvd {
 
@@ -295,6 +296,363 @@ __global__ __launch_bounds__(NT) void chol_rl_kernel(const QrDesc* __restrict__ 
     }
 }
 
+// ---------------------------------------------------------------- register-resident Cholesky
+// For l <= 288 the lower triangle of G fits in the registers of one workgroup
+// of 12 waves as 16 x 16 MFMA accumulator tiles: waves 1..11 hold the tiles
+// (diagonal ones included; column-major order, round robin, so that every
+// panel's remaining tiles are spread evenly), so the trailing updates never go
+// back to memory, and wave 0 runs the dependent chain of the method.  Each
+// tile is held transposed, T_IK = G_IK^T, which makes it the B operand of the
+// panel product and the output of the update:
+//   panel     L_IJ^T = L_JJ^-1 T_IJ          (then copied to LDS and to d.L)
+//   update    T_IK  -= L_KJ L_IJ^T            (operands from the LDS panel copy)
+// Right-looking by 16-column panels.  The chain of panel J (sub-diagonal tile
+// J + 1, then diagonal block J + 1 updated and factored) is wave 0's: the
+// owners of those two tiles copy them to LDS after their last update in the
+// previous panel, and wave 0 forms the sub-diagonal block of L, updates and
+// factors diagonal block J + 1 while the other waves form the rest of panel
+// J and update their tiles.  Two barriers per panel, ordering LDS only:
+// nothing the kernel writes to global memory is read back in it.  Same
+// outputs as the kernel above (L column-major in d.L, the diagonal-block
+// inverses in d.D, the breakdown flag); G is only read.
+constexpr int CHR_T = 18;                                                 // tile rows: l <= 288
+constexpr int CHR_NT = 768;                                               // 12 waves
+constexpr int CHR_OW = CHR_NT / 64 - 1;                                   // waves holding tiles
+constexpr int CHR_NPW = (CHR_T * (CHR_T + 1) / 2 + CHR_OW - 1) / CHR_OW;  // tiles per such wave
+
+struct ChrLds {
+    double Lp[CHR_T * 16][17];  // column panel J of L, by absolute row (staging tiles at the start)
+    double Lb[16][17], Li[16][17], Dt[16][17];
+    double Ts[16][17], Td[16][17];  // the next sub-diagonal and diagonal tiles (transposed)
+    double g0[CHR_T * 16];          // diagonal of G (pivot reference)
+    int bad;
+};
+
+// Workgroup barrier ordering LDS only (the global stores stay in flight).
+__device__ __forceinline__ void chr_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Lane T of every row of 16 lanes, broadcast to its row (one 64-bit DPP
+// row_newbcast move).
+template <int T> __device__ __forceinline__ double row_bcast16(double v)
+{
+    const long long u = __builtin_bit_cast(long long, v);
+    return __builtin_bit_cast(double, (long long)__builtin_amdgcn_mov_dpp(u, 0x150 + T, 0xF, 0xF, false));
+}
+
+template <int I, int N, typename F> __device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// The diagonal block factorisation of the register-resident kernel: the same
+// arithmetic as chol_factor_diag (so the same L and inverse to the bit), laid
+// out for latency, since every dependent FP64 operation costs tens of cycles.
+// Lane (r, q) holds row r of the block and the column values travel by row
+// broadcasts; every lane updates its whole row (the entries above the
+// diagonal become garbage that is never read: the lower triangle depends on
+// lower entries only); the pivot test is off the dependent chain; and each
+// column's inverse pivot is kept apart, so that the substitution for the
+// inverse (its step t needs column t of L only) can run beside the later
+// columns of the factorisation.
+__device__ __forceinline__ void chr_factor_diag(double (*Dt)[17], double (*Lb)[17], double (*Li)[17],
+                                                const double* g0, int J0, int w, int* bad_s,
+                                                GLB double* __restrict__ Dg)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, lq = lane >> 4;
+    double a[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const double v = Dt[r][c];
+        a[c] = (r < w && c < w) ? v : (r == c ? 1.0 : 0.0);
+    }
+    const double gv = g0[J0 + (r < w ? r : 0)];
+    const double gref = (r < w) ? gv : 1.0;
+    double piv = 1.0;
+    // lane (r, q) holds row r of columns 4 q .. 4 q + 3 of the inverse; step t
+    // takes x_t = s_t / L_tt from row t of its column group
+    double sv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) sv[j] = (r == 4 * lq + j) ? 1.0 : 0.0;
+    double dinv = 1.0, inv_prev = 1.0;
+    // (rows r <= t keep their value: they add -0 x_t, which changes no value)
+    auto inverse_step = [&](auto T_, double it) {
+        constexpr int T = decltype(T_)::value;
+        const double na = (r > T) ? -a[T] : -0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double xt = row_bcast16<T>(sv[j]) * it;
+            sv[j] = fma(na, xt, sv[j]);
+        }
+    };
+    // column C of the factorisation beside step C - 1 of the substitution
+    static_for<0, 16>([&](auto C_) {
+        constexpr int C = decltype(C_)::value;
+        const double pc = row_bcast16<C>(a[C]);
+        const double inv = rsqrt_f64(pc);
+        const double lrc = a[C] * inv;
+        a[C] = lrc;
+        static_for<C + 1, 16>([&](auto K_) {
+            constexpr int K = decltype(K_)::value;
+            a[K] = fma(-lrc, row_bcast16<K>(lrc), a[K]);
+        });
+        piv = (r == C) ? pc : piv;
+        dinv = (r == C) ? inv : dinv;
+        if constexpr (C > 0) inverse_step(std::integral_constant<int, C - 1>{}, inv_prev);
+        inv_prev = inv;
+        __builtin_amdgcn_sched_barrier(0);
+    });
+    inverse_step(std::integral_constant<int, 15>{}, inv_prev);
+    const bool bad = __any(!(piv > CHOL_PIVOT_REL * gref) || !(piv < INFINITY));
+    if (lane < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) Lb[r][c] = (c <= r) ? a[c] : 0.0;
+    }
+    if (lane == 0) *bad_s = bad ? 1 : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int c = 4 * lq + j;
+        const double x = (c <= r) ? sv[j] * dinv : 0.0;
+        Li[r][c] = x;
+        Dg[(int64_t)(J0 / 16) * 256 + r * 16 + c] = (r < w && c < w) ? x : 0.0;
+    }
+}
+
+// A tile coordinate the compiler must re-read in every pass: without it the
+// per-tile addresses (loop invariant) are hoisted out of the panel loop and
+// spilled.
+__device__ __forceinline__ int chr_opaque(int t)
+{
+    asm volatile("" : "+s"(t));
+    return t;
+}
+
+// Tile (I, K) of G into an LDS block: dst[l16][lq + 4 r] = G[16 I + l16][16 K + lq + 4 r]
+// (trans = false: the tile as it is) or dst[lq + 4 r][l16] = the same value
+// (trans = true: the transposed tile T_IK in accumulator layout).
+__device__ __forceinline__ void chr_load_tile(double (*dst)[17], const GLB double* __restrict__ G, int l, int I, int K,
+                                              int l16, int lq, bool trans)
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + l16, j = 16 * K + lq + 4 * r;
+        const double v = ld_or0(G, (int64_t)i * l + j, i < l && j < l);
+        if (trans)
+            dst[lq + 4 * r][l16] = v;
+        else
+            dst[l16][lq + 4 * r] = v;
+    }
+}
+
+// wave 0: per panel J, the sub-diagonal block of L, diagonal block J + 1
+// updated and factored; the diagonal blocks of L are written out during the
+// next panel pass
+__device__ __forceinline__ void chr_chain_path(ChrLds& s, const GLB double* __restrict__ G,
+                                               GLB double* __restrict__ Rt, GLB double* __restrict__ Dg,
+                                               GLB int* __restrict__ flag, int l, int T)
+{
+    const int lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
+    __builtin_amdgcn_s_setprio(3);  // the dependent chain first on this SIMD
+    // the pivot references, diagonal block 0 and the first sub-diagonal and
+    // diagonal tiles, loaded here so that block 0 is factored while the other
+    // waves load their tiles
+    for (int i = lane; i < l; i += 64) s.g0[i] = G[(int64_t)i * l + i];
+    chr_load_tile(s.Dt, G, l, 0, 0, l16, lq, false);
+    if (T > 1) {
+        chr_load_tile(s.Ts, G, l, 1, 0, l16, lq, true);
+        chr_load_tile(s.Td, G, l, 1, 1, l16, lq, true);
+    }
+    wave_lds_fence();
+    chr_factor_diag(s.Dt, s.Lb, s.Li, s.g0, 0, min(16, l), &s.bad, Dg);
+    chr_barrier();  // tiles loaded, block 0 factored
+    for (int J = 0; J < T; ++J) {
+        if (s.bad) {
+            if (lane == 0) *flag = 1;
+            return;
+        }
+        const int K1 = J + 1;
+        if (K1 < T) {
+            // L_{J+1,J}^T = L_JJ^-1 T_{J+1,J}; o[r] = L[16 K1 + l16][16 J + lq + 4 r]
+            dbl4 o = {0, 0, 0, 0};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+                o = __builtin_amdgcn_mfma_f64_16x16x4f64(s.Li[l16][4 * s4 + lq], s.Ts[4 * s4 + lq][l16], o, 0, 0, 0);
+            const int i = 16 * K1 + l16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = lq + 4 * r;
+                const bool ok = i < l && 16 * J + c < l;
+                s.Lp[i][c] = ok ? o[r] : 0.0;
+                if (ok) Rt[(int64_t)(16 * J + c) * l + i] = o[r];
+            }
+            wave_lds_fence();
+            // diagonal block J + 1 -= L_{J+1,J} L_{J+1,J}^T
+            dbl4 t;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) t[r] = s.Td[lq + 4 * r][l16];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const double v = s.Lp[i][4 * s4 + lq];
+                t = __builtin_amdgcn_mfma_f64_16x16x4f64(-v, v, t, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) s.Dt[l16][lq + 4 * r] = t[r];
+        }
+        chr_barrier();  // panel J in Lp (diagonal block J of L written out by a tile wave)
+        if (K1 == T) break;
+        chr_factor_diag(s.Dt, s.Lb, s.Li, s.g0, 16 * K1, min(16, l - 16 * K1), &s.bad, Dg);
+        chr_barrier();  // block J + 1 factored, trailing tiles updated
+    }
+}
+
+// waves 1..11: the tiles.  Tile t (column-major over the lower triangle,
+// column K starting at t = K T - K (K - 1) / 2) is held by tile wave t mod
+// CHR_OW in slot t / CHR_OW, so each pass finds its tiles by arithmetic.
+__device__ __forceinline__ void chr_tile_path(ChrLds& s, const GLB double* __restrict__ G, GLB double* __restrict__ Rt,
+                                              int l, int T, int w)
+{
+    const int lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
+    const int ntile = T * (T + 1) / 2;
+    const int nslot = w < ntile ? (ntile - w + CHR_OW - 1) / CHR_OW : 0;
+    auto base = [&](int K) { return K * T - K * (K - 1) / 2; };
+    auto first_slot = [&](int t) { return t > w ? (t - w + CHR_OW - 1) / CHR_OW : 0; };  // first slot with tile >= t
+    int tc[CHR_NPW];  // I + 256 K; invalid tiles get K = CHR_T
+    {
+        int K = 0, rem = w;  // column K holds T - K tiles
+#pragma unroll
+        for (int g = 0; g < CHR_NPW; ++g) {
+            const bool ok = g < nslot;
+            while (ok && rem >= T - K) {
+                rem -= T - K;
+                ++K;
+            }
+            tc[g] = ok ? (K + rem) + 256 * K : 256 * CHR_T;
+            rem += CHR_OW;
+        }
+    }
+    // coalesced loads (tile row lq + 4 r, column l16), then a transpose through
+    // this wave's 16 staging rows of Lp into T_IK[lq + 4 r][l16] = G[16 I + l16][16 K + lq + 4 r]
+    dbl4 acc[CHR_NPW];
+#pragma unroll
+    for (int g = 0; g < CHR_NPW; ++g) {
+        const int I = tc[g] & 255, K = tc[g] >> 8;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * I + lq + 4 * r, j = 16 * K + l16;
+            acc[g][r] = ld_or0(G, (int64_t)i * l + j, K < T && i < l && j < l);
+        }
+    }
+    // (one wave's LDS operations execute in order, so the staging rows are
+    // reused from tile to tile without a wait)
+    double(*stg)[17] = &s.Lp[16 * w];
+#pragma unroll
+    for (int g = 0; g < CHR_NPW; ++g) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) stg[lq + 4 * r][l16] = acc[g][r];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[g][r] = stg[l16][lq + 4 * r];
+    }
+    chr_barrier();  // tiles loaded, block 0 factored (the staging rows are free again)
+    // panel product of the tile in slot G: L_IJ^T = L_JJ^-1 T_IJ; o[r] = L[16 I + l16][16 J + lq + 4 r]
+    auto panel = [&](auto G_, int J) {
+        constexpr int Gs = decltype(G_)::value;
+        const int I = chr_opaque(tc[Gs]) & 255;
+        dbl4 o = {0, 0, 0, 0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+            o = __builtin_amdgcn_mfma_f64_16x16x4f64(s.Li[l16][4 * s4 + lq], acc[Gs][s4], o, 0, 0, 0);
+        const int i = 16 * I + l16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = lq + 4 * r;
+            const bool ok = i < l && 16 * J + c < l;
+            s.Lp[i][c] = ok ? o[r] : 0.0;
+            if (ok) Rt[(int64_t)(16 * J + c) * l + i] = o[r];
+        }
+    };
+    for (int J = 0; J < T; ++J) {
+        if (s.bad) return;
+        const int K1 = J + 1;
+        const int bJ = base(J), bK1 = base(K1);
+        const int tdiag = bK1;  // tile (J + 1, J + 1), wave 0's
+        const bool more = K1 < T;
+        // the sub-diagonal tile first (it feeds diagonal block J + 1)
+        if (w == CHR_OW - 1) {  // diagonal block J of L, factored by wave 0
+            const int wd = min(16, l - 16 * J);
+            for (int e = lane; e < 256; e += 64) {
+                const int r = e >> 4, c = e & 15;
+                if (r < wd && c < wd) Rt[(int64_t)(16 * J + c) * l + 16 * J + r] = (c <= r) ? s.Lb[r][c] : 0.0;
+            }
+        }
+        const int glo = first_slot(bJ + 2), ghi = first_slot(bK1);  // column J below the sub-diagonal tile
+        static_for<0, CHR_NPW>([&](auto G_) {
+            if (decltype(G_)::value >= glo && decltype(G_)::value < ghi) panel(G_, J);
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        const int gdiag = (more && tdiag % CHR_OW == w) ? tdiag / CHR_OW : -1;
+        chr_barrier();  // panel J in Lp
+        if (!more) break;
+        // the trailing tiles (columns > J, diagonal block J + 1 is wave 0's):
+        // T_IK -= L_KJ L_IJ^T; the next panel's sub-diagonal and diagonal
+        // tiles go to LDS for wave 0 after this, their last update
+        const int gfirst = first_slot(bK1);
+        const int tnsub = bK1 + 1, tndiag = base(K1 + 1);  // tiles (J + 2, J + 1) and (J + 2, J + 2)
+        const bool next = K1 + 1 < T;
+        const int gnsub = (next && tnsub % CHR_OW == w) ? tnsub / CHR_OW : -1;
+        const int gndiag = (next && tndiag % CHR_OW == w) ? tndiag / CHR_OW : -1;
+#pragma unroll
+        for (int g = 0; g < CHR_NPW; ++g) {
+            if (g >= gfirst && g < nslot && g != gdiag) {
+                const int t = chr_opaque(tc[g]);
+                const int I = t & 255, K = t >> 8;
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    const int k = 4 * s4 + lq;
+                    acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(-s.Lp[16 * K + l16][k], s.Lp[16 * I + l16][k],
+                                                                  acc[g], 0, 0, 0);
+                }
+                if (g == gnsub) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) s.Ts[lq + 4 * r][l16] = acc[g][r];
+                }
+                if (g == gndiag) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) s.Td[lq + 4 * r][l16] = acc[g][r];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        chr_barrier();  // block J + 1 factored, trailing tiles updated
+    }
+}
+
+__global__ __launch_bounds__(CHR_NT) void chol_reg_kernel(const QrDesc* __restrict__ descs)
+{
+    __shared__ ChrLds s;
+    const QrDesc& d = descs[blockIdx.x];
+    if (d.Qout == nullptr || *to_glb(d.flag)) return;
+    const int l = d.l, T = (l + 15) / 16;
+    const GLB double* __restrict__ G = to_glb((const double*)d.G);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave == 0)
+        chr_chain_path(s, G, to_glb(d.L), to_glb(d.D), to_glb(d.flag), l, T);
+    else
+        chr_tile_path(s, G, to_glb(d.L), l, T, wave - 1);
+}
+
 // ---------------------------------------------------------------- Q = M L^-T
 // One wave per 16 rows of M.  With Q^T = L^-1 M^T, block column C of Q^T is
 // D_C (M^T[C] - L[C, :C] Q^T[:C]); both products are FP64 MFMA chains, the
@@ -378,6 +736,71 @@ __global__ __launch_bounds__(64) void trsm_kernel(const QrDesc* __restrict__ des
         const int r = e / l, c = e % l;
         Qout[(int64_t)(r0 + r) * l + c] = Qs[r * ldq + c];
     }
+}
+
+// The same substitution for l <= 288 with the wave's 16 rows of Q held in
+// registers: block C of Q^T leaves the D_C product in accumulator layout,
+// res[C][r] = Q[r0 + l16][16 C + lq + 4 r], which is exactly the B operand
+// layout in which the later blocks read it, so no LDS round trip (and no
+// barrier) separates the blocks, and the loads of L for a whole block are
+// issued together.  The products are those of trsm_kernel in the same order
+// (the same Q to the bit).
+template <typename TS>
+__global__ __launch_bounds__(64) void trsm_reg_kernel(const QrDesc* __restrict__ descs,
+                                                      const int* __restrict__ row_begin, int nprob, int from_min)
+{
+    const int t = blockIdx.x;
+    const int2 wi_ = wg_item(row_begin, t);
+    const QrDesc& d = descs[wi_.x];
+    if (d.Qout == nullptr || *to_glb(d.flag)) return;
+    const int l = d.l, rows = d.rows, T = (l + 15) / 16;
+    const int r0 = wi_.y * 16;
+    const GLB double* __restrict__ Rt = to_glb((const double*)d.L);  // Rt[k * l + r] = L[r][k]
+    const GLB double* __restrict__ D = to_glb((const double*)d.D);
+    GLB double* __restrict__ Qout = to_glb(d.Qout);
+    const GLB TS* __restrict__ src = from_min ? (const GLB TS*)d.Min : (const GLB TS*)d.Qout;
+    const int lane = threadIdx.x, l16 = lane & 15, lq = lane >> 4;
+    const int row = r0 + l16;
+    const bool row_ok = row < rows;
+    dbl4 res[CHR_T];
+    static_for<0, CHR_T>([&](auto C_) {
+        constexpr int C = decltype(C_)::value;
+        if (C < T) {
+            // acc[r] = (M^T - L Q^T)[16 C + lq + 4 r][row]
+            dbl4 acc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = 16 * C + lq + 4 * r;
+                acc[r] = to_f64(ld_or0(src, (int64_t)row * l + c, row_ok && c < l));
+            }
+            const int ra = 16 * C + l16;  // row of L supplying the A operand
+            double av[4 * C + 1];
+#pragma unroll
+            for (int j = 0; j < 4 * C; ++j) av[j] = -ld_or0(Rt, (int64_t)(4 * j + lq) * l + ra, ra < l);
+            static_for<0, C>([&](auto Cp_) {
+                constexpr int Cp = decltype(Cp_)::value;
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[4 * Cp + s4], res[Cp][s4], acc, 0, 0, 0);
+            });
+            // res[C] = D_C acc: accumulator register s is the B operand row 4 s + lane / 16
+            const GLB double* Dc = D + (int64_t)C * 256;
+            dbl4 o = {0, 0, 0, 0};
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) o = __builtin_amdgcn_mfma_f64_16x16x4f64(Dc[l16 * 16 + 4 * s2 + lq], acc[s2], o, 0, 0, 0);
+            res[C] = o;
+        }
+    });
+    static_for<0, CHR_T>([&](auto C_) {
+        constexpr int C = decltype(C_)::value;
+        if (C < T) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = 16 * C + lq + 4 * r;
+                if (row_ok && c < l) Qout[(int64_t)row * l + c] = res[C][r];
+            }
+        }
+    });
 }
 
 // ---------------------------------------------------------------- adjoint helpers
@@ -969,6 +1392,10 @@ static size_t chol_lds_bytes(int max_l)
 hipError_t launch_chol(const QrDesc* d, int nprob, int max_l, hipStream_t s)
 {
     if (nprob <= 0) return hipSuccess;
+    if (max_l <= CHR_T * 16) {
+        hipLaunchKernelGGL(chol_reg_kernel, dim3(nprob), dim3(CHR_NT), 0, s, d);
+        return hipGetLastError();
+    }
     const size_t lds = chol_lds_bytes(max_l);
     if (max_l <= 256)
         hipLaunchKernelGGL(chol_rl_kernel<256>, dim3(nprob), dim3(256), lds, s, d);
@@ -981,6 +1408,15 @@ hipError_t launch_trsm(const QrDesc* d, const int* row_begin, int nprob, int tot
                        int src_elem, int max_l, hipStream_t s)
 {
     if (total_blocks <= 0) return hipSuccess;
+    if (max_l <= CHR_T * 16) {
+        if (from_min && src_elem == E_F32)
+            hipLaunchKernelGGL(trsm_reg_kernel<float>, dim3(total_blocks), dim3(64), 0, s, d, row_begin, nprob, from_min);
+        else if (!from_min || src_elem == E_F64)
+            hipLaunchKernelGGL(trsm_reg_kernel<double>, dim3(total_blocks), dim3(64), 0, s, d, row_begin, nprob, from_min);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     const size_t lds = (size_t)16 * (max_l + 1) * sizeof(double);
     if (from_min && src_elem == E_F32)
         hipLaunchKernelGGL(trsm_kernel<float>, dim3(total_blocks), dim3(64), lds, s, d, row_begin, nprob, from_min);
