@@ -71,6 +71,18 @@ template <typename T> __device__ __forceinline__ T ld_or0(const GLB T* p, int64_
     return ok ? v : (T)0;
 }
 
+// Store written through this XCD's L2 (an agent-scope relaxed store): the
+// line is not left dirty in L2, where the end-of-kernel write-back, which the
+// next kernel waits for, would have to flush it.  Used for the rows the
+// Jacobi rounds rotate (measured: the other large outputs gain nothing).
+template <typename T> __device__ __forceinline__ void st_through(GLB T* p, T v)
+{
+    if constexpr (sizeof(T) == 8 || sizeof(T) == 4)
+        __hip_atomic_store((T*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = v;
+}
+
 // Wave-level reductions (64 lanes) with shuffles.
 __device__ __forceinline__ double wave_sum(double v)
 {

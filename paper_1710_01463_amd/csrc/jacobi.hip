@@ -148,7 +148,7 @@ __device__ void apply_rotation(const ChunkSeq& cs, double (&pre)[JPF], const int
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int g = rowmap[rt * 16 + lq + 4 * r];
-                if (gc < ncols && g >= 0) M[(int64_t)g * ldm + gc] = acc[r];
+                if (gc < ncols && g >= 0) st_through(&M[(int64_t)g * ldm + gc], acc[r]);
             }
         }
         __syncthreads();
@@ -186,7 +186,7 @@ __device__ void apply_rotation_resident(const ChunkSeq& cs, double (&res)[NS][JP
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int g = rowmap[rt * 16 + lq + 4 * r];
-                if (gc < ncols && g >= 0) M[(int64_t)g * ldm + gc] = acc[r];
+                if (gc < ncols && g >= 0) st_through(&M[(int64_t)g * ldm + gc], acc[r]);
             }
         }
         __syncthreads();

@@ -168,7 +168,7 @@ __device__ __forceinline__ void chol_factor_diag(double (*Dt)[17], double (*Lb)[
 }
 
 template <int NT>
-__global__ __launch_bounds__(NT) void chol_rl_kernel(const QrDesc* __restrict__ descs)
+__global__ __launch_bounds__(NT) void chol_rl_kernel(const QrDesc* __restrict__ descs, int min_l)
 {
     constexpr int NW = NT / 64;
     static_assert(NW >= 2, "wave 0 factors while the others update");
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(NT) void chol_rl_kernel(const QrDesc* __restrict__ 
     __shared__ double Dt[16][17];
     __shared__ int bad_s;
     const QrDesc& d = descs[blockIdx.x];
-    if (d.Qout == nullptr || *to_glb(d.flag)) return;
+    if (d.Qout == nullptr || d.l < min_l || *to_glb(d.flag)) return;
     const int l = d.l;
     double* g0 = dyn;
     double(*Lp)[17] = reinterpret_cast<double(*)[17]>(dyn + ((l + 1) & ~1));
@@ -643,7 +643,7 @@ __global__ __launch_bounds__(CHR_NT) void chol_reg_kernel(const QrDesc* __restri
 {
     __shared__ ChrLds s;
     const QrDesc& d = descs[blockIdx.x];
-    if (d.Qout == nullptr || *to_glb(d.flag)) return;
+    if (d.Qout == nullptr || d.l > CHR_T * 16 || *to_glb(d.flag)) return;
     const int l = d.l, T = (l + 15) / 16;
     const GLB double* __restrict__ G = to_glb((const double*)d.G);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -660,14 +660,15 @@ __global__ __launch_bounds__(CHR_NT) void chol_reg_kernel(const QrDesc* __restri
 // wave's 16 rows of Q stay in LDS; no other wave reads them.
 template <typename TS>
 __global__ __launch_bounds__(64) void trsm_kernel(const QrDesc* __restrict__ descs,
-                                                  const int* __restrict__ row_begin, int nprob, int from_min)
+                                                  const int* __restrict__ row_begin, int nprob, int from_min,
+                                                  int min_l)
 {
     extern __shared__ double Qs[];  // 16 x (l + 1)
     const int t = blockIdx.x;
     const int2 wi_ = wg_item(row_begin, t);
     const int b = wi_.x;
     const QrDesc& d = descs[b];
-    if (d.Qout == nullptr || *to_glb(d.flag)) return;
+    if (d.Qout == nullptr || d.l < min_l || *to_glb(d.flag)) return;
     const int l = d.l, rows = d.rows;
     const int ldq = l + 1;
     const int r0 = wi_.y * 16;
@@ -752,7 +753,7 @@ __global__ __launch_bounds__(64) void trsm_reg_kernel(const QrDesc* __restrict__
     const int t = blockIdx.x;
     const int2 wi_ = wg_item(row_begin, t);
     const QrDesc& d = descs[wi_.x];
-    if (d.Qout == nullptr || *to_glb(d.flag)) return;
+    if (d.Qout == nullptr || d.l > CHR_T * 16 || *to_glb(d.flag)) return;
     const int l = d.l, rows = d.rows, T = (l + 15) / 16;
     const int r0 = wi_.y * 16;
     const GLB double* __restrict__ Rt = to_glb((const double*)d.L);  // Rt[k * l + r] = L[r][k]
@@ -1391,49 +1392,42 @@ static size_t chol_lds_bytes(int max_l)
 
 hipError_t launch_chol(const QrDesc* d, int nprob, int max_l, hipStream_t s)
 {
+    // problems with l <= 288 take the register-resident kernel, wider ones the
+    // general one (each kernel skips the other's problems)
     if (nprob <= 0) return hipSuccess;
-    if (max_l <= CHR_T * 16) {
-        hipLaunchKernelGGL(chol_reg_kernel, dim3(nprob), dim3(CHR_NT), 0, s, d);
-        return hipGetLastError();
-    }
+    hipLaunchKernelGGL(chol_reg_kernel, dim3(nprob), dim3(CHR_NT), 0, s, d);
+    if (max_l <= CHR_T * 16) return hipGetLastError();
     const size_t lds = chol_lds_bytes(max_l);
-    if (max_l <= 256)
-        hipLaunchKernelGGL(chol_rl_kernel<256>, dim3(nprob), dim3(256), lds, s, d);
-    else
-        hipLaunchKernelGGL(chol_rl_kernel<512>, dim3(nprob), dim3(512), lds, s, d);
+    hipLaunchKernelGGL(chol_rl_kernel<512>, dim3(nprob), dim3(512), lds, s, d, CHR_T * 16 + 1);
     return hipGetLastError();
 }
 
 hipError_t launch_trsm(const QrDesc* d, const int* row_begin, int nprob, int total_blocks, int from_min,
                        int src_elem, int max_l, hipStream_t s)
 {
+    // row blocks of problems with l <= 288 take the register-resident kernel,
+    // those of wider ones the general one (each kernel skips the other's)
     if (total_blocks <= 0) return hipSuccess;
-    if (max_l <= CHR_T * 16) {
-        if (from_min && src_elem == E_F32)
-            hipLaunchKernelGGL(trsm_reg_kernel<float>, dim3(total_blocks), dim3(64), 0, s, d, row_begin, nprob, from_min);
-        else if (!from_min || src_elem == E_F64)
-            hipLaunchKernelGGL(trsm_reg_kernel<double>, dim3(total_blocks), dim3(64), 0, s, d, row_begin, nprob, from_min);
-        else
-            return hipErrorInvalidValue;
-        return hipGetLastError();
-    }
-    const size_t lds = (size_t)16 * (max_l + 1) * sizeof(double);
-    if (from_min && src_elem == E_F32)
-        hipLaunchKernelGGL(trsm_kernel<float>, dim3(total_blocks), dim3(64), lds, s, d, row_begin, nprob, from_min);
-    else if (!from_min || src_elem == E_F64)
-        hipLaunchKernelGGL(trsm_kernel<double>, dim3(total_blocks), dim3(64), lds, s, d, row_begin, nprob, from_min);
+    const bool f32 = from_min && src_elem == E_F32;
+    if (!f32 && from_min && src_elem != E_F64) return hipErrorInvalidValue;
+    if (f32)
+        hipLaunchKernelGGL(trsm_reg_kernel<float>, dim3(total_blocks), dim3(64), 0, s, d, row_begin, nprob, from_min);
     else
-        return hipErrorInvalidValue;
+        hipLaunchKernelGGL(trsm_reg_kernel<double>, dim3(total_blocks), dim3(64), 0, s, d, row_begin, nprob, from_min);
+    if (max_l <= CHR_T * 16) return hipGetLastError();
+    const size_t lds = (size_t)16 * (max_l + 1) * sizeof(double);
+    const int min_l = CHR_T * 16 + 1;
+    if (f32)
+        hipLaunchKernelGGL(trsm_kernel<float>, dim3(total_blocks), dim3(64), lds, s, d, row_begin, nprob, from_min, min_l);
+    else
+        hipLaunchKernelGGL(trsm_kernel<double>, dim3(total_blocks), dim3(64), lds, s, d, row_begin, nprob, from_min, min_l);
     return hipGetLastError();
 }
 
 hipError_t init_qr_kernels()
 {
-    hipError_t e = hipFuncSetAttribute((const void*)chol_rl_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)chol_rl_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)chol_lds_bytes(CHOL_MAX_L));
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)chol_rl_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)chol_lds_bytes(CHOL_MAX_L));
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void*)trsm_upper_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        16 * (CHOL_MAX_L + 1) * (int)sizeof(double));
