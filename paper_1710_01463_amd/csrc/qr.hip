@@ -743,9 +743,9 @@ __global__ __launch_bounds__(64) void trsm_kernel(const QrDesc* __restrict__ des
 // registers: block C of Q^T leaves the D_C product in accumulator layout,
 // res[C][r] = Q[r0 + l16][16 C + lq + 4 r], which is exactly the B operand
 // layout in which the later blocks read it, so no LDS round trip (and no
-// barrier) separates the blocks, and the loads of L for a whole block are
-// issued together.  The products are those of trsm_kernel in the same order
-// (the same Q to the bit).
+// barrier) separates the blocks, and the loads for a block are issued one
+// block ahead.  The products are those of trsm_kernel in the same order, up
+// to exact sign changes (the same Q to the bit, up to the sign of zeros).
 template <typename TS>
 __global__ __launch_bounds__(64) void trsm_reg_kernel(const QrDesc* __restrict__ descs,
                                                       const int* __restrict__ row_begin, int nprob, int from_min)
@@ -764,32 +764,56 @@ __global__ __launch_bounds__(64) void trsm_reg_kernel(const QrDesc* __restrict__
     const int row = r0 + l16;
     const bool row_ok = row < rows;
     dbl4 res[CHR_T];
+    // the operands of block C: the 4 row values of M^T (acc init), the 4 C
+    // values of L (A operand of the update) and the diagonal-block inverse;
+    // double-buffered, so that block C + 1's loads are in flight while block
+    // C's dependent MFMA chain runs.  They are kept as loaded (no select or
+    // negation that would wait for them): out-of-range elements read an
+    // in-range one, which only reaches padded rows of Q (never stored, and
+    // each lane's row is independent) or padded columns (cancelled by the
+    // zero-padded D_C), and the chain accumulates -(M^T - L Q^T), negated
+    // back after the D_C product (sign changes are exact).
+    double lv[2][4 * CHR_T];
+    TS mv[2][4];
+    double dv[2][4];
+    auto issue = [&](auto C_, auto B_) {
+        constexpr int C = decltype(C_)::value, Bf = decltype(B_)::value;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = 16 * C + lq + 4 * r;
+            mv[Bf][r] = src[(row_ok && c < l) ? (int64_t)row * l + c : 0];
+        }
+        const int ra = 16 * C + l16;  // row of L supplying the A operand
+#pragma unroll
+        for (int j = 0; j < 4 * C; ++j) lv[Bf][j] = Rt[ra < l ? (int64_t)(4 * j + lq) * l + ra : 0];
+        const GLB double* Dc = D + (int64_t)C * 256;
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) dv[Bf][s2] = Dc[l16 * 16 + 4 * s2 + lq];
+    };
+    issue(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
     static_for<0, CHR_T>([&](auto C_) {
-        constexpr int C = decltype(C_)::value;
+        constexpr int C = decltype(C_)::value, Bf = C % 2;
         if (C < T) {
-            // acc[r] = (M^T - L Q^T)[16 C + lq + 4 r][row]
-            dbl4 acc;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int c = 16 * C + lq + 4 * r;
-                acc[r] = to_f64(ld_or0(src, (int64_t)row * l + c, row_ok && c < l));
+            if constexpr (C + 1 < CHR_T) {
+                if (C + 1 < T) issue(std::integral_constant<int, C + 1>{}, std::integral_constant<int, 1 - Bf>{});
             }
-            const int ra = 16 * C + l16;  // row of L supplying the A operand
-            double av[4 * C + 1];
+            __builtin_amdgcn_sched_barrier(0);
+            // nacc[r] = -(M^T - L Q^T)[16 C + lq + 4 r][row]
+            dbl4 nacc;
 #pragma unroll
-            for (int j = 0; j < 4 * C; ++j) av[j] = -ld_or0(Rt, (int64_t)(4 * j + lq) * l + ra, ra < l);
+            for (int r = 0; r < 4; ++r) nacc[r] = -to_f64(mv[Bf][r]);
             static_for<0, C>([&](auto Cp_) {
                 constexpr int Cp = decltype(Cp_)::value;
 #pragma unroll
                 for (int s4 = 0; s4 < 4; ++s4)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[4 * Cp + s4], res[Cp][s4], acc, 0, 0, 0);
+                    nacc = __builtin_amdgcn_mfma_f64_16x16x4f64(lv[Bf][4 * Cp + s4], res[Cp][s4], nacc, 0, 0, 0);
             });
-            // res[C] = D_C acc: accumulator register s is the B operand row 4 s + lane / 16
-            const GLB double* Dc = D + (int64_t)C * 256;
+            // res[C] = D_C acc = -(D_C nacc): accumulator register s is the B operand row 4 s + lane / 16
             dbl4 o = {0, 0, 0, 0};
 #pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2) o = __builtin_amdgcn_mfma_f64_16x16x4f64(Dc[l16 * 16 + 4 * s2 + lq], acc[s2], o, 0, 0, 0);
-            res[C] = o;
+            for (int s2 = 0; s2 < 4; ++s2) o = __builtin_amdgcn_mfma_f64_16x16x4f64(dv[Bf][s2], nacc[s2], o, 0, 0, 0);
+            res[C] = -o;
+            __builtin_amdgcn_sched_barrier(0);
         }
     });
     static_for<0, CHR_T>([&](auto C_) {
