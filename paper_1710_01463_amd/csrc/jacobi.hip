@@ -72,26 +72,34 @@ __device__ __forceinline__ void jac_rotation(double a, double b, double g, doubl
     sn = rot ? y * t : 0.0;
 }
 
-// Loads the 32 x JCH chunk (rows via rowmap, columns c0..) of M into registers.
-__device__ __forceinline__ void load_chunk(double (&pre)[JPF], const GLB double* __restrict__ M, int64_t ldm,
-                                           int ncols, int c0, const int* rowmap)
+// Loads the 32 x JCH chunk (rows via rowmap, columns c0..) of M into registers
+// as loaded (an out-of-range element reads an in-range one) and returns the
+// in-range mask, applied when the chunk is written to LDS: nothing consumes
+// a loaded value before then, so the loads stay in flight (across the inner
+// sweep for the rows of P).
+__device__ __forceinline__ uint32_t load_chunk(double (&pre)[JPF], const GLB double* __restrict__ M, int64_t ldm,
+                                               int ncols, int c0, const int* rowmap)
 {
     const int tid = threadIdx.x;
+    uint32_t ok = 0;
 #pragma unroll
     for (int i = 0; i < JPF; ++i) {
         const int e = tid + JT * i;
         const int a = e / JCH, cc = e % JCH;
         const int gr = rowmap[a], gc = c0 + cc;
-        pre[i] = ld_or0(M, (int64_t)gr * ldm + gc, gr >= 0 && gc < ncols);
+        const bool in = gr >= 0 && gc < ncols;
+        pre[i] = M[in ? (int64_t)gr * ldm + gc : 0];
+        ok |= (uint32_t)in << i;
     }
+    return ok;
 }
-__device__ __forceinline__ void store_chunk(const double (&pre)[JPF], double (*Xs)[JCH + 1])
+__device__ __forceinline__ void store_chunk(const double (&pre)[JPF], uint32_t ok, double (*Xs)[JCH + 1])
 {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < JPF; ++i) {
         const int e = tid + JT * i;
-        Xs[e / JCH][e % JCH] = pre[i];
+        Xs[e / JCH][e % JCH] = ((ok >> i) & 1u) ? pre[i] : 0.0;
     }
 }
 
@@ -110,28 +118,28 @@ struct ChunkSeq {
         ncols = in_x ? C : R;
         c0 = (in_x ? ci : ci - ncx) * JCH;
     }
-    __device__ void load(double (&pre)[JPF], int ci, const int* rowmap) const
+    __device__ uint32_t load(double (&pre)[JPF], int ci, const int* rowmap) const
     {
         GLB double* M;
         int64_t ldm;
         int ncols, c0;
         select(ci, M, ldm, ncols, c0);
-        load_chunk(pre, M, ldm, ncols, c0, rowmap);
+        return load_chunk(pre, M, ldm, ncols, c0, rowmap);
     }
 };
 
 // rows <- Ps (32 x 32) * rows for every chunk of the sequence, in place; the
 // first chunk is already in pre, each next chunk is prefetched while the
 // current one is multiplied.
-__device__ void apply_rotation(const ChunkSeq& cs, double (&pre)[JPF], const int* rowmap,
+__device__ void apply_rotation(const ChunkSeq& cs, double (&pre)[JPF], uint32_t ok, const int* rowmap,
                                double (*Ps)[JR + 1], double (*Xs)[JCH + 1])
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
     for (int ci = 0; ci < cs.nct; ++ci) {
-        store_chunk(pre, Xs);
+        store_chunk(pre, ok, Xs);
         __syncthreads();
-        if (ci + 1 < cs.nct) cs.load(pre, ci + 1, rowmap);
+        if (ci + 1 < cs.nct) ok = cs.load(pre, ci + 1, rowmap);
         GLB double* M;
         int64_t ldm;
         int ncols, c0;
@@ -160,8 +168,8 @@ constexpr int JAC_INNER_SWEEPS = 1;
 // rows <- Ps * rows for chunks already held in registers (res[ch] = chunk ch of
 // the sequence): no global load on the way, only the LDS transpose for MFMA.
 template <int NS>
-__device__ void apply_rotation_resident(const ChunkSeq& cs, double (&res)[NS][JPF], int ch0, int ch_end,
-                                        const int* rowmap, double (*Ps)[JR + 1], double (*Xs)[JCH + 1])
+__device__ void apply_rotation_resident(const ChunkSeq& cs, double (&res)[NS][JPF], const uint32_t (&ok)[NS], int ch0,
+                                        int ch_end, const int* rowmap, double (*Ps)[JR + 1], double (*Xs)[JCH + 1])
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, lq = lane >> 4;
@@ -169,7 +177,7 @@ __device__ void apply_rotation_resident(const ChunkSeq& cs, double (&res)[NS][JP
     for (int sl = 0; sl < NS; ++sl) {
         const int ci = ch0 + sl;
         if (ci >= ch_end) break;  // uniform; no load below
-        store_chunk(res[sl], Xs);
+        store_chunk(res[sl], ok[sl], Xs);
         __syncthreads();
         GLB double* M;
         int64_t ldm;
@@ -256,6 +264,7 @@ __device__ __forceinline__ int jacobi_pair_task(const JacDesc& d, int slot, int 
     // chunk; with JKS = 2 the two halves are added through LDS
     constexpr int NRX = RX > 0 ? RX : 1;
     double resx[NRX][JPF];
+    uint32_t okx[NRX] = {};
     {
         const int tile = wave % JTILES;
         const int wi = tile / (JR / 16), wj = tile % (JR / 16), half = wave / JTILES;
@@ -272,22 +281,22 @@ __device__ __forceinline__ int jacobi_pair_task(const JacDesc& d, int slot, int 
             // every X chunk in flight at once (slots past the row length
             // re-read chunk 0 and are not used)
 #pragma unroll
-            for (int ch = 0; ch < RX; ++ch) load_chunk(resx[ch], X, ldx, C, (ch < seq.ncx ? ch : 0) * JCH, rowmap);
+            for (int ch = 0; ch < RX; ++ch) okx[ch] = load_chunk(resx[ch], X, ldx, C, (ch < seq.ncx ? ch : 0) * JCH, rowmap);
 #pragma unroll
             for (int ch = 0; ch < RX; ++ch) {
                 if (ch > 0 && ch >= seq.ncx) break;  // uniform; no load below
-                store_chunk(resx[ch], Xs);
+                store_chunk(resx[ch], okx[ch], Xs);
                 __syncthreads();
                 gram_chunk();
                 __syncthreads();
             }
         } else {
             double pre[JPF];
-            load_chunk(pre, X, ldx, C, 0, rowmap);
+            uint32_t okc = load_chunk(pre, X, ldx, C, 0, rowmap);
             for (int c0 = 0; c0 < C; c0 += JCH) {
-                store_chunk(pre, Xs);
+                store_chunk(pre, okc, Xs);
                 __syncthreads();
-                if (c0 + JCH < C) load_chunk(pre, X, ldx, C, c0 + JCH, rowmap);
+                if (c0 + JCH < C) okc = load_chunk(pre, X, ldx, C, c0 + JCH, rowmap);
                 gram_chunk();
                 __syncthreads();
             }
@@ -307,7 +316,8 @@ __device__ __forceinline__ int jacobi_pair_task(const JacDesc& d, int slot, int 
     }
     // streaming: prefetch the first chunk of the rotation phase; it lands during the inner solve
     double pre[JPF];
-    if constexpr (RX == 0) seq.load(pre, 0, rowmap);
+    uint32_t okpre = 0;
+    if constexpr (RX == 0) okpre = seq.load(pre, 0, rowmap);
     __syncthreads();
     // symmetrise from the upper triangle, identity for P
     for (int e = tid; e < JR * JR; e += JT) {
@@ -339,11 +349,12 @@ __device__ __forceinline__ int jacobi_pair_task(const JacDesc& d, int slot, int 
     // resident: the rows of P, in flight during the inner solve
     constexpr int NRP = RP > 0 ? RP : 1;
     double resp[NRP][JPF];
+    uint32_t okp[NRP] = {};
     if constexpr (RX > 0) {
 #pragma unroll
         for (int sl = 0; sl < RP; ++sl) {
             const int ci = seq.ncx + sl;
-            seq.load(resp[sl], ci < seq.nct ? ci : 0, rowmap);
+            okp[sl] = seq.load(resp[sl], ci < seq.nct ? ci : 0, rowmap);
         }
     }
 
@@ -399,10 +410,10 @@ __device__ __forceinline__ int jacobi_pair_task(const JacDesc& d, int slot, int 
 
     // ---- apply the accumulated rotation to the rows of X and of P
     if constexpr (RX > 0) {
-        apply_rotation_resident<RX>(seq, resx, 0, seq.ncx, rowmap, Ps, Xs);
-        apply_rotation_resident<RP>(seq, resp, seq.ncx, seq.nct, rowmap, Ps, Xs);
+        apply_rotation_resident<RX>(seq, resx, okx, 0, seq.ncx, rowmap, Ps, Xs);
+        apply_rotation_resident<RP>(seq, resp, okp, seq.ncx, seq.nct, rowmap, Ps, Xs);
     } else {
-        apply_rotation(seq, pre, rowmap, Ps, Xs);
+        apply_rotation(seq, pre, okpre, rowmap, Ps, Xs);
     }
     return JAC_RAN;
 }
