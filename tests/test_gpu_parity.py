@@ -245,3 +245,34 @@ def test_persistent_jacobi_equals_round_launches(lib):
             plan.close()
         (a, wa, ka), (b, wb, kb) = res
         assert all(torch.equal(x, y) for x, y in zip(a, b)) and torch.equal(wa, wb) and torch.equal(ka, kb), (dtype, full)
+
+
+def test_qr_kernel_classes_in_one_batch(lib):
+    """One plan whose sketch widths straddle the register-resident Cholesky and
+    substitution (l <= 288) and the general kernels (l > 288), so every
+    orthonormalisation launches both kernel classes, each skipping the other's
+    problems: l = 288, 289, 320, and 50 (the last with n >= 2 l, so its small
+    SVD also runs the triangular-factor Cholesky QR).  Every problem against
+    the oracle at the FP64 bars."""
+    shapes = [(360, 330, 272, 16), (330, 400, 273, 16), (400, 352, 304, 16), (200, 180, 40, 10)]
+    mats, probs = [], []
+    for b, (m, n, k, p) in enumerate(shapes):
+        mats.append(wl.make_matrix(m, n, wl.spectrum_power(min(m, n), 1.5), seed=880 + b))
+        probs.append(dict(m=m, n=n, k=k, p=p, q=2, seed=890 + b))
+    assert [min(pr["k"] + pr["p"], pr["m"], pr["n"]) for pr in probs] == [288, 289, 320, 50]
+    plan = lib.Plan(probs, torch.float64, "f64", graph=True)
+    outs, w, kk, info = plan.execute([dev(A) for A in mats])
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    w, kk = w.cpu().numpy(), kk.cpu().numpy()
+    for b, (A, pr) in enumerate(zip(mats, probs)):
+        ref = oracle.rsvd(A, pr["k"], pr["p"], pr["q"], pr["seed"])
+        U, S, VT = host(outs[b][0]), host(outs[b][1]), host(outs[b][2])
+        assert kk[b] == ref.k_kept, b
+        assert np.all(np.abs(S - ref.S) <= sigma_tol_f64(ref.S)), b
+        assert abs(w[b] - ref.w) <= 1e-10 * max(ref.w, 1e-300) + 1e-13 * np.sum(A * A), b
+        align_and_compare(U, VT, ref.U, ref.VT, ref.S, 1e-8)
+        kk2 = len(S)
+        assert np.linalg.norm(U.T @ U - np.eye(kk2)) < 100 * max(A.shape) * EPS, b
+        assert np.linalg.norm(VT @ VT.T - np.eye(kk2)) < 100 * max(A.shape) * EPS, b
+    plan.close()
