@@ -95,6 +95,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
     const int l16 = lane & 15;
     const int lq = lane >> 4;
 
+    const bool wave_in = m0 + wm < d.M && n0 + wn < d.N;  // uniform per wave
     Acc4 acc[FM][FN];
 #pragma unroll
     for (int a = 0; a < FM; ++a)
@@ -164,7 +165,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
         __syncthreads();
         if (k0 + BK < K) load_tiles(k0 + BK);
 
-        if constexpr (GK == GK_F64) {
+        // a wave whose sub-tile lies wholly outside C (the last tile row or
+        // column of a size that is not a tile multiple) leaves its MFMAs out
+        if (!wave_in) {
+        } else if constexpr (GK == GK_F64) {
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
                 double av[FM], bv[FN];
