@@ -363,19 +363,40 @@ __device__ __forceinline__ int jacobi_pair_task(const JacDesc& d, int slot, int 
     // (pair pi_ rows) x (pair pj_ cols) of H and/or the 2 x 2 block (pair pi_
     // rows) x (columns 2 pj_, 2 pj_ + 1) of P: with 2 JHB <= 1024 threads the
     // two updates run side by side on separate threads.  H is double-buffered
-    // so one barrier per step suffices.
+    // so one barrier per step suffices.  With separate P threads, only the H
+    // threads compute the rotations: they leave the step's JNP rotations in an
+    // LDS table (double-buffered by step parity), and the P threads apply step
+    // s - 1's during step s (nothing in H depends on P), and the last one after
+    // the loop; the same products as when every thread computes them.
     const bool on_h = !JSPLIT || tid < JHB;
     const bool on_p = !JSPLIT || tid >= JHB;
     const int pr_i = (tid % JHB) / JNP, pr_j = tid % JNP;
     static_assert(JNP <= 64 && 64 % JNP == 0, "every wave computes all plane-pair rotations");
+    __shared__ double rot_tab[2][JNP][2];
     int cur = 0;
     const int nsteps = cross ? JAC_B : JR - 1;
-    for (int isw = 0; isw < JAC_INNER_SWEEPS; ++isw) {
-        for (int step = 0; step < nsteps; ++step) {
-            // full: round-robin over all JR rows; cross: row p of block I with
-            // row JAC_B + (p + step) mod JAC_B of block J
-            const int p_i = cross ? pr_i : rr_block(pr_i, step, JR);
-            const int q_i = cross ? JAC_B + ((pr_i + step) & (JAC_B - 1)) : rr_block(JR - 1 - pr_i, step, JR);
+    const int gsteps = JAC_INNER_SWEEPS * nsteps;
+    auto rows_i = [&](int step, int& p_i, int& q_i) {
+        // full: round-robin over all JR rows; cross: row p of block I with
+        // row JAC_B + (p + step) mod JAC_B of block J
+        p_i = cross ? pr_i : rr_block(pr_i, step, JR);
+        q_i = cross ? JAC_B + ((pr_i + step) & (JAC_B - 1)) : rr_block(JR - 1 - pr_i, step, JR);
+    };
+    auto update_p = [&](int p_i, int q_i, double ci, double si) {
+        if (si != 0.0) {
+            const int c0 = 2 * pr_j, c1 = 2 * pr_j + 1;
+            const double x0 = Ps[p_i][c0], x1 = Ps[p_i][c1], y0 = Ps[q_i][c0], y1 = Ps[q_i][c1];
+            Ps[p_i][c0] = ci * x0 - si * y0;
+            Ps[p_i][c1] = ci * x1 - si * y1;
+            Ps[q_i][c0] = si * x0 + ci * y0;
+            Ps[q_i][c1] = si * x1 + ci * y1;
+        }
+    };
+    for (int gs = 0; gs < gsteps; ++gs) {
+        const int step = gs % nsteps;
+        if (on_h) {
+            int p_i, q_i;
+            rows_i(step, p_i, q_i);
             const int p_j = cross ? pr_j : rr_block(pr_j, step, JR);
             const int q_j = cross ? JAC_B + ((pr_j + step) & (JAC_B - 1)) : rr_block(JR - 1 - pr_j, step, JR);
             double (*H)[JR + 1] = Hbuf[cur];
@@ -386,26 +407,33 @@ __device__ __forceinline__ int jacobi_pair_task(const JacDesc& d, int slot, int 
             double cj, sj;
             jac_rotation(H[p_j][p_j], H[q_j][q_j], H[p_j][q_j], tol, cj, sj);
             const double ci = __shfl(cj, pr_i, 64), si = __shfl(sj, pr_i, 64);
-            if (on_h) {
-                const double b00 = H[p_i][p_j], b01 = H[p_i][q_j], b10 = H[q_i][p_j], b11 = H[q_i][q_j];
-                const double t00 = ci * b00 - si * b10, t01 = ci * b01 - si * b11;
-                const double t10 = si * b00 + ci * b10, t11 = si * b01 + ci * b11;
-                Hn[p_i][p_j] = t00 * cj - t01 * sj;
-                Hn[p_i][q_j] = t00 * sj + t01 * cj;
-                Hn[q_i][p_j] = t10 * cj - t11 * sj;
-                Hn[q_i][q_j] = t10 * sj + t11 * cj;
+            const double b00 = H[p_i][p_j], b01 = H[p_i][q_j], b10 = H[q_i][p_j], b11 = H[q_i][q_j];
+            const double t00 = ci * b00 - si * b10, t01 = ci * b01 - si * b11;
+            const double t10 = si * b00 + ci * b10, t11 = si * b01 + ci * b11;
+            Hn[p_i][p_j] = t00 * cj - t01 * sj;
+            Hn[p_i][q_j] = t00 * sj + t01 * cj;
+            Hn[q_i][p_j] = t10 * cj - t11 * sj;
+            Hn[q_i][q_j] = t10 * sj + t11 * cj;
+            if constexpr (JSPLIT) {
+                if (tid < JNP) {
+                    rot_tab[gs & 1][tid][0] = cj;
+                    rot_tab[gs & 1][tid][1] = sj;
+                }
+            } else {
+                update_p(p_i, q_i, ci, si);
             }
-            if (on_p && si != 0.0) {
-                const int c0 = 2 * pr_j, c1 = 2 * pr_j + 1;
-                const double x0 = Ps[p_i][c0], x1 = Ps[p_i][c1], y0 = Ps[q_i][c0], y1 = Ps[q_i][c1];
-                Ps[p_i][c0] = ci * x0 - si * y0;
-                Ps[p_i][c1] = ci * x1 - si * y1;
-                Ps[q_i][c0] = si * x0 + ci * y0;
-                Ps[q_i][c1] = si * x1 + ci * y1;
-            }
-            cur ^= 1;
-            __syncthreads();
+        } else if (gs > 0) {
+            int p_i, q_i;
+            rows_i((gs - 1) % nsteps, p_i, q_i);
+            update_p(p_i, q_i, rot_tab[(gs - 1) & 1][pr_i][0], rot_tab[(gs - 1) & 1][pr_i][1]);
         }
+        cur ^= 1;
+        __syncthreads();
+    }
+    if (JSPLIT && on_p && gsteps > 0) {
+        int p_i, q_i;
+        rows_i((gsteps - 1) % nsteps, p_i, q_i);
+        update_p(p_i, q_i, rot_tab[(gsteps - 1) & 1][pr_i][0], rot_tab[(gsteps - 1) & 1][pr_i][1]);
     }
 
     // ---- apply the accumulated rotation to the rows of X and of P
