@@ -128,75 +128,109 @@ struct ChunkSeq {
     }
 };
 
-// rows <- Ps (32 x 32) * rows for every chunk of the sequence, in place; the
-// first chunk is already in pre, each next chunk is prefetched while the
-// current one is multiplied.
+// The rotation phase: rows <- Ps (JR x JR) * rows, one JCH-column chunk at a
+// time staged in Xs.  Wave w forms row tile w % 2 of two column tiles,
+// w / 2 and w / 2 + JCT / 2: the tiles share their A operand (the wave's 16
+// rows of Ps, loaded once per phase), their two MFMA chains are interleaved,
+// and the destination rows come from registers; a column tile wholly outside
+// the matrix is left out.  Each output element is the same k-ordered sum as
+// one 16 x 16 x JR product.
+constexpr int JWAVES = JT / 64;
+constexpr int JRT = JR / 16, JCT = JCH / 16;  // row and column tiles of a chunk
+static_assert(JRT == 2 && JCT == JWAVES, "two column tiles of one row tile per wave");
+
+struct RotLane {
+    double pa[JR / 4];  // A operands: Ps rows of the wave's row tile
+    int grow[4];        // destination rows of the lane's outputs (-1: padding)
+};
+
+__device__ __forceinline__ void rot_lane_init(RotLane& rl, const double (*Ps)[JR + 1], const int* rowmap)
+{
+    const int lane = threadIdx.x & 63, rt = (threadIdx.x >> 6) % JRT;
+    const int l16 = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int k = 0; k < JR / 4; ++k) rl.pa[k] = Ps[rt * 16 + l16][4 * k + lq];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rl.grow[r] = rowmap[rt * 16 + lq + 4 * r];
+}
+
+__device__ __forceinline__ void rotate_chunk(const RotLane& rl, const double (*Xs)[JCH + 1], GLB double* M,
+                                             int64_t ldm, int ncols, int c0)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int tj0 = wave / JRT, tj1 = tj0 + JCT / 2;
+    if (c0 + 16 * tj0 >= ncols) return;  // wave-uniform: both tiles outside
+    const bool two = c0 + 16 * tj1 < ncols;
+    double b0[JR / 4], b1[JR / 4];
+#pragma unroll
+    for (int k = 0; k < JR / 4; ++k) b0[k] = Xs[4 * k + lq][16 * tj0 + l16];
+    dbl4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    if (two) {
+#pragma unroll
+        for (int k = 0; k < JR / 4; ++k) b1[k] = Xs[4 * k + lq][16 * tj1 + l16];
+#pragma unroll
+        for (int k = 0; k < JR / 4; ++k) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(rl.pa[k], b0[k], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(rl.pa[k], b1[k], acc1, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < JR / 4; ++k) acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(rl.pa[k], b0[k], acc0, 0, 0, 0);
+    }
+    const int gc0 = c0 + 16 * tj0 + l16, gc1 = c0 + 16 * tj1 + l16;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int g = rl.grow[r];
+        if (g >= 0) {
+            GLB double* row = M + (int64_t)g * ldm;
+            if (gc0 < ncols) st_through(&row[gc0], acc0[r]);
+            if (two && gc1 < ncols) st_through(&row[gc1], acc1[r]);
+        }
+    }
+}
+
+// Every chunk of the sequence, in place; the first chunk is already in pre,
+// each next chunk is prefetched while the current one is multiplied.
 __device__ void apply_rotation(const ChunkSeq& cs, double (&pre)[JPF], uint32_t ok, const int* rowmap,
                                double (*Ps)[JR + 1], double (*Xs)[JCH + 1])
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int l16 = lane & 15, lq = lane >> 4;
+    RotLane rl;
     for (int ci = 0; ci < cs.nct; ++ci) {
         store_chunk(pre, ok, Xs);
         __syncthreads();
+        if (ci == 0) rot_lane_init(rl, Ps, rowmap);
         if (ci + 1 < cs.nct) ok = cs.load(pre, ci + 1, rowmap);
         GLB double* M;
         int64_t ldm;
         int ncols, c0;
         cs.select(ci, M, ldm, ncols, c0);
-        // (JR / 16) x (JCH / 16) output tiles of 16 x 16, spread over the waves
-        for (int tl = wave; tl < (JR / 16) * (JCH / 16); tl += JT / 64) {
-            const int rt = tl / (JCH / 16), tj = tl % (JCH / 16);
-            dbl4 acc = {0, 0, 0, 0};
-#pragma unroll
-            for (int kk = 0; kk < JR; kk += 4)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ps[rt * 16 + l16][kk + lq], Xs[kk + lq][tj * 16 + l16], acc,
-                                                           0, 0, 0);
-            const int gc = c0 + tj * 16 + l16;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int g = rowmap[rt * 16 + lq + 4 * r];
-                if (gc < ncols && g >= 0) st_through(&M[(int64_t)g * ldm + gc], acc[r]);
-            }
-        }
+        rotate_chunk(rl, Xs, M, ldm, ncols, c0);
         __syncthreads();
     }
 }
 
 constexpr int JAC_INNER_SWEEPS = 1;
 
-// rows <- Ps * rows for chunks already held in registers (res[ch] = chunk ch of
-// the sequence): no global load on the way, only the LDS transpose for MFMA.
+// Chunks already held in registers (res[ch] = chunk ch0 + ch of the
+// sequence): no global load on the way, only the LDS transpose for MFMA.
 template <int NS>
 __device__ void apply_rotation_resident(const ChunkSeq& cs, double (&res)[NS][JPF], const uint32_t (&ok)[NS], int ch0,
                                         int ch_end, const int* rowmap, double (*Ps)[JR + 1], double (*Xs)[JCH + 1])
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int l16 = lane & 15, lq = lane >> 4;
+    RotLane rl;
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
         const int ci = ch0 + sl;
         if (ci >= ch_end) break;  // uniform; no load below
         store_chunk(res[sl], ok[sl], Xs);
         __syncthreads();
+        if (sl == 0) rot_lane_init(rl, Ps, rowmap);
         GLB double* M;
         int64_t ldm;
         int ncols, c0;
         cs.select(ci, M, ldm, ncols, c0);
-        for (int tl = wave; tl < (JR / 16) * (JCH / 16); tl += JT / 64) {
-            const int rt = tl / (JCH / 16), tj = tl % (JCH / 16);
-            dbl4 acc = {0, 0, 0, 0};
-#pragma unroll
-            for (int kk = 0; kk < JR; kk += 4)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ps[rt * 16 + l16][kk + lq], Xs[kk + lq][tj * 16 + l16], acc,
-                                                           0, 0, 0);
-            const int gc = c0 + tj * 16 + l16;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int g = rowmap[rt * 16 + lq + 4 * r];
-                if (gc < ncols && g >= 0) st_through(&M[(int64_t)g * ldm + gc], acc[r]);
-            }
-        }
+        rotate_chunk(rl, Xs, M, ldm, ncols, c0);
         __syncthreads();
     }
 }
@@ -330,13 +364,20 @@ __device__ __forceinline__ int jacobi_pair_task(const JacDesc& d, int slot, int 
     const bool cross = d.cross_rounds && round >= 2;
     __syncthreads();
     // any_rot bit 0: some off-diagonal entry above the threshold (the sweep
-    // has not converged); bit 1: some entry that this round rotates
-    for (int e = tid; e < JR * JR; e += JT) {
-        const int i = e / JR, j = e % JR;
-        if (i < j) {
-            const double a = Hbuf[0][i][i], c = Hbuf[0][j][j], g = Hbuf[0][i][j];
-            if (jac_needs(a, c, g, tol)) atomicOr(&any_rot, (!cross || (i < JAC_B && j >= JAC_B)) ? 3 : 1);
+    // has not converged); bit 1: some entry that this round rotates.  The
+    // lanes' findings are combined by ballot and each wave sets the flag with
+    // one LDS atomic (lane atomics on one word serialise across the CU).
+    {
+        int need = 0;
+        for (int e = tid; e < JR * JR; e += JT) {
+            const int i = e / JR, j = e % JR;
+            if (i < j) {
+                const double a = Hbuf[0][i][i], c = Hbuf[0][j][j], g = Hbuf[0][i][j];
+                if (jac_needs(a, c, g, tol)) need |= (!cross || (i < JAC_B && j >= JAC_B)) ? 3 : 1;
+            }
         }
+        const unsigned long long any1 = __ballot(need & 1), any2 = __ballot(need & 2);
+        if (lane == 0 && any1) atomicOr(&any_rot, any2 ? 3 : 1);
     }
     __syncthreads();
     if (tid == 0) {
@@ -373,47 +414,68 @@ __device__ __forceinline__ int jacobi_pair_task(const JacDesc& d, int slot, int 
     const int pr_i = (tid % JHB) / JNP, pr_j = tid % JNP;
     static_assert(JNP <= 64 && 64 % JNP == 0, "every wave computes all plane-pair rotations");
     __shared__ double rot_tab[2][JNP][2];
-    int cur = 0;
     const int nsteps = cross ? JAC_B : JR - 1;
     const int gsteps = JAC_INNER_SWEEPS * nsteps;
-    auto rows_i = [&](int step, int& p_i, int& q_i) {
-        // full: round-robin over all JR rows; cross: row p of block I with
-        // row JAC_B + (p + step) mod JAC_B of block J
-        p_i = cross ? pr_i : rr_block(pr_i, step, JR);
-        q_i = cross ? JAC_B + ((pr_i + step) & (JAC_B - 1)) : rr_block(JR - 1 - pr_i, step, JR);
+    // The plane pair indices at step 0 and their advance by one step, instead
+    // of the schedule's modulo arithmetic at every step: in a full round
+    // (round robin over all JR rows) a position other than 0 moves to the next
+    // one, JR wrapping to 1; in a cross round row p of block I stays and row
+    // JAC_B + (p + step) mod JAC_B of block J moves on, JR wrapping to JAC_B.
+    // Both cycles have nsteps steps, so the indices are back at their step-0
+    // values after every inner sweep.  The advance is plain arithmetic (JR is
+    // a power of two and a position at most JR after the increment), so no
+    // lane branches on it.
+    static_assert((JR & (JR - 1)) == 0, "power-of-two pair rows");
+    const unsigned q_back = cross ? JR - JAC_B : JR - 1;  // JR -> restart row
+    auto first = [&](int pr, unsigned& p, unsigned& q, unsigned& p_inc) {
+        p = cross ? pr : rr_block(pr, 0, JR);
+        q = cross ? JAC_B + pr : rr_block(JR - 1 - pr, 0, JR);
+        p_inc = (cross || pr == 0) ? 0u : 1u;
     };
-    auto update_p = [&](int p_i, int q_i, double ci, double si) {
+    auto advance = [&](unsigned& p, unsigned& q, unsigned p_inc) {
+        p += p_inc;
+        p -= __umul24(p / JR, JR - 1);
+        q += 1;
+        q -= __umul24(q / JR, q_back);
+        __builtin_assume(p < JR);
+        __builtin_assume(q < JR);
+    };
+    // element (r, c) of a JR x (JR + 1) LDS array, the row offset by a 24-bit
+    // multiply (indices below JR)
+    auto at = [](double (*M)[JR + 1], unsigned r, unsigned c) -> double& {
+        return (&M[0][0])[__umul24(r, JR + 1) + c];
+    };
+    auto update_p = [&](unsigned p_i, unsigned q_i, double ci, double si) {
         if (si != 0.0) {
-            const int c0 = 2 * pr_j, c1 = 2 * pr_j + 1;
-            const double x0 = Ps[p_i][c0], x1 = Ps[p_i][c1], y0 = Ps[q_i][c0], y1 = Ps[q_i][c1];
-            Ps[p_i][c0] = ci * x0 - si * y0;
-            Ps[p_i][c1] = ci * x1 - si * y1;
-            Ps[q_i][c0] = si * x0 + ci * y0;
-            Ps[q_i][c1] = si * x1 + ci * y1;
+            const unsigned c0 = 2 * pr_j, c1 = 2 * pr_j + 1;
+            const double x0 = at(Ps, p_i, c0), x1 = at(Ps, p_i, c1), y0 = at(Ps, q_i, c0), y1 = at(Ps, q_i, c1);
+            at(Ps, p_i, c0) = ci * x0 - si * y0;
+            at(Ps, p_i, c1) = ci * x1 - si * y1;
+            at(Ps, q_i, c0) = si * x0 + ci * y0;
+            at(Ps, q_i, c1) = si * x1 + ci * y1;
         }
     };
+    unsigned p_i, q_i, p_j, q_j;  // this step's rows of pair pr_i and pair pr_j (P threads: the previous step's)
+    unsigned inc_i, inc_j;
+    first(pr_i, p_i, q_i, inc_i);
+    first(pr_j, p_j, q_j, inc_j);
     for (int gs = 0; gs < gsteps; ++gs) {
-        const int step = gs % nsteps;
         if (on_h) {
-            int p_i, q_i;
-            rows_i(step, p_i, q_i);
-            const int p_j = cross ? pr_j : rr_block(pr_j, step, JR);
-            const int q_j = cross ? JAC_B + ((pr_j + step) & (JAC_B - 1)) : rr_block(JR - 1 - pr_j, step, JR);
-            double (*H)[JR + 1] = Hbuf[cur];
-            double (*Hn)[JR + 1] = Hbuf[cur ^ 1];
+            double (*H)[JR + 1] = Hbuf[gs & 1];
+            double (*Hn)[JR + 1] = Hbuf[(gs & 1) ^ 1];
             // each lane computes the rotation of plane pair pr_j (= lane % JNP,
             // so every wave holds all JNP of them) and takes pair pr_i's from
             // the lane that computed it: one rotation per thread, not two
             double cj, sj;
-            jac_rotation(H[p_j][p_j], H[q_j][q_j], H[p_j][q_j], tol, cj, sj);
+            jac_rotation(at(H, p_j, p_j), at(H, q_j, q_j), at(H, p_j, q_j), tol, cj, sj);
             const double ci = __shfl(cj, pr_i, 64), si = __shfl(sj, pr_i, 64);
-            const double b00 = H[p_i][p_j], b01 = H[p_i][q_j], b10 = H[q_i][p_j], b11 = H[q_i][q_j];
+            const double b00 = at(H, p_i, p_j), b01 = at(H, p_i, q_j), b10 = at(H, q_i, p_j), b11 = at(H, q_i, q_j);
             const double t00 = ci * b00 - si * b10, t01 = ci * b01 - si * b11;
             const double t10 = si * b00 + ci * b10, t11 = si * b01 + ci * b11;
-            Hn[p_i][p_j] = t00 * cj - t01 * sj;
-            Hn[p_i][q_j] = t00 * sj + t01 * cj;
-            Hn[q_i][p_j] = t10 * cj - t11 * sj;
-            Hn[q_i][q_j] = t10 * sj + t11 * cj;
+            at(Hn, p_i, p_j) = t00 * cj - t01 * sj;
+            at(Hn, p_i, q_j) = t00 * sj + t01 * cj;
+            at(Hn, q_i, p_j) = t10 * cj - t11 * sj;
+            at(Hn, q_i, q_j) = t10 * sj + t11 * cj;
             if constexpr (JSPLIT) {
                 if (tid < JNP) {
                     rot_tab[gs & 1][tid][0] = cj;
@@ -422,19 +484,16 @@ __device__ __forceinline__ int jacobi_pair_task(const JacDesc& d, int slot, int 
             } else {
                 update_p(p_i, q_i, ci, si);
             }
+            advance(p_i, q_i, inc_i);
+            advance(p_j, q_j, inc_j);
         } else if (gs > 0) {
-            int p_i, q_i;
-            rows_i((gs - 1) % nsteps, p_i, q_i);
             update_p(p_i, q_i, rot_tab[(gs - 1) & 1][pr_i][0], rot_tab[(gs - 1) & 1][pr_i][1]);
+            advance(p_i, q_i, inc_i);
         }
-        cur ^= 1;
         __syncthreads();
     }
-    if (JSPLIT && on_p && gsteps > 0) {
-        int p_i, q_i;
-        rows_i((gsteps - 1) % nsteps, p_i, q_i);
+    if (JSPLIT && on_p && gsteps > 0)
         update_p(p_i, q_i, rot_tab[(gsteps - 1) & 1][pr_i][0], rot_tab[(gsteps - 1) & 1][pr_i][1]);
-    }
 
     // ---- apply the accumulated rotation to the rows of X and of P
     if constexpr (RX > 0) {
