@@ -72,35 +72,38 @@ __device__ __forceinline__ void jac_rotation(double a, double b, double g, doubl
     sn = rot ? y * t : 0.0;
 }
 
-// Loads the 32 x JCH chunk (rows via rowmap, columns c0..) of M into registers
-// as loaded (an out-of-range element reads an in-range one) and returns the
-// in-range mask, applied when the chunk is written to LDS: nothing consumes
-// a loaded value before then, so the loads stay in flight (across the inner
-// sweep for the rows of P).
+// A 32 x JCH chunk in registers: slot k of lane (l16, lq) of wave w holds
+// element (4 k + lq, 16 w + l16), the B operand layout of a 16 x 16 x 4 FP64
+// MFMA for column tile w, so the rotation multiplies the rows where they were
+// loaded (each load instruction reads four rows of 128 contiguous bytes).
+constexpr int JWAVES = JT / 64;
+static_assert(JCH == 16 * JWAVES && JR == 4 * JPF, "one column tile per wave, one row per slot and lane row");
+
+// Loads the chunk (rows via rowmap, columns c0..) of M as loaded (an
+// out-of-range element reads an in-range one) and returns the in-range mask,
+// applied where the chunk is used: nothing consumes a loaded value before
+// then, so the loads stay in flight (across the inner sweep for the rows of P).
 __device__ __forceinline__ uint32_t load_chunk(double (&pre)[JPF], const GLB double* __restrict__ M, int64_t ldm,
                                                int ncols, int c0, const int* rowmap)
 {
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int gc = c0 + 16 * wave + (lane & 15), lq = lane >> 4;
     uint32_t ok = 0;
 #pragma unroll
-    for (int i = 0; i < JPF; ++i) {
-        const int e = tid + JT * i;
-        const int a = e / JCH, cc = e % JCH;
-        const int gr = rowmap[a], gc = c0 + cc;
+    for (int k = 0; k < JPF; ++k) {
+        const int gr = rowmap[4 * k + lq];
         const bool in = gr >= 0 && gc < ncols;
-        pre[i] = M[in ? (int64_t)gr * ldm + gc : 0];
-        ok |= (uint32_t)in << i;
+        pre[k] = M[in ? (int64_t)gr * ldm + gc : 0];
+        ok |= (uint32_t)in << k;
     }
     return ok;
 }
 __device__ __forceinline__ void store_chunk(const double (&pre)[JPF], uint32_t ok, double (*Xs)[JCH + 1])
 {
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = 16 * wave + (lane & 15), lq = lane >> 4;
 #pragma unroll
-    for (int i = 0; i < JPF; ++i) {
-        const int e = tid + JT * i;
-        Xs[e / JCH][e % JCH] = ((ok >> i) & 1u) ? pre[i] : 0.0;
-    }
+    for (int k = 0; k < JPF; ++k) Xs[4 * k + lq][c] = ((ok >> k) & 1u) ? pre[k] : 0.0;
 }
 
 // The augmented rows [X | P] of the pair, JCH columns at a time: chunk ci < ncx
@@ -128,110 +131,98 @@ struct ChunkSeq {
     }
 };
 
-// The rotation phase: rows <- Ps (JR x JR) * rows, one JCH-column chunk at a
-// time staged in Xs.  Wave w forms row tile w % 2 of two column tiles,
-// w / 2 and w / 2 + JCT / 2: the tiles share their A operand (the wave's 16
-// rows of Ps, loaded once per phase), their two MFMA chains are interleaved,
-// and the destination rows come from registers; a column tile wholly outside
-// the matrix is left out.  Each output element is the same k-ordered sum as
-// one 16 x 16 x JR product.
-constexpr int JWAVES = JT / 64;
-constexpr int JRT = JR / 16, JCT = JCH / 16;  // row and column tiles of a chunk
-static_assert(JRT == 2 && JCT == JWAVES, "two column tiles of one row tile per wave");
+// The rotation phase: rows <- Ps (JR x JR) * rows, chunk by chunk, straight
+// from the registers the chunk was loaded into: wave w forms both 16-row
+// tiles of column tile w (two interleaved MFMA chains over the same B
+// operands, the A operands being all of Ps, loaded once per phase), and the
+// destination rows come from registers; no LDS staging and no barrier.  A
+// column tile wholly outside the matrix is left out.  Each output element is
+// the same k-ordered sum as one 16 x 16 x JR product.
+constexpr int JRT = JR / 16;  // row tiles
+static_assert(JRT == 2, "two row tiles per pair");
 
 struct RotLane {
-    double pa[JR / 4];  // A operands: Ps rows of the wave's row tile
-    int grow[4];        // destination rows of the lane's outputs (-1: padding)
+    double pa[JRT][JR / 4];  // A operands: Ps rows of each row tile
+    int grow[JRT][4];        // destination rows of the lane's outputs (-1: padding)
 };
 
 __device__ __forceinline__ void rot_lane_init(RotLane& rl, const double (*Ps)[JR + 1], const int* rowmap)
 {
-    const int lane = threadIdx.x & 63, rt = (threadIdx.x >> 6) % JRT;
+    const int lane = threadIdx.x & 63;
     const int l16 = lane & 15, lq = lane >> 4;
 #pragma unroll
-    for (int k = 0; k < JR / 4; ++k) rl.pa[k] = Ps[rt * 16 + l16][4 * k + lq];
+    for (int rt = 0; rt < JRT; ++rt) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) rl.grow[r] = rowmap[rt * 16 + lq + 4 * r];
+        for (int k = 0; k < JR / 4; ++k) rl.pa[rt][k] = Ps[rt * 16 + l16][4 * k + lq];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rl.grow[rt][r] = rowmap[rt * 16 + lq + 4 * r];
+    }
 }
 
-__device__ __forceinline__ void rotate_chunk(const RotLane& rl, const double (*Xs)[JCH + 1], GLB double* M,
+// One chunk held in x (as loaded, with its in-range mask ok) at columns c0..
+// of M.
+__device__ __forceinline__ void rotate_chunk(const RotLane& rl, const double (&x)[JPF], uint32_t ok, GLB double* M,
                                              int64_t ldm, int ncols, int c0)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int l16 = lane & 15, lq = lane >> 4;
-    const int tj0 = wave / JRT, tj1 = tj0 + JCT / 2;
-    if (c0 + 16 * tj0 >= ncols) return;  // wave-uniform: both tiles outside
-    const bool two = c0 + 16 * tj1 < ncols;
-    double b0[JR / 4], b1[JR / 4];
-#pragma unroll
-    for (int k = 0; k < JR / 4; ++k) b0[k] = Xs[4 * k + lq][16 * tj0 + l16];
+    const int gc = c0 + 16 * wave + (lane & 15);
+    if (c0 + 16 * wave >= ncols) return;  // wave-uniform: the column tile is outside
     dbl4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    if (two) {
 #pragma unroll
-        for (int k = 0; k < JR / 4; ++k) b1[k] = Xs[4 * k + lq][16 * tj1 + l16];
-#pragma unroll
-        for (int k = 0; k < JR / 4; ++k) {
-            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(rl.pa[k], b0[k], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(rl.pa[k], b1[k], acc1, 0, 0, 0);
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < JR / 4; ++k) acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(rl.pa[k], b0[k], acc0, 0, 0, 0);
+    for (int k = 0; k < JR / 4; ++k) {
+        // padding rows read as zeros (an out-of-range value is any in-range
+        // element, and 0 * inf would not vanish)
+        const double b = ((ok >> k) & 1u) ? x[k] : 0.0;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(rl.pa[0][k], b, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(rl.pa[1][k], b, acc1, 0, 0, 0);
     }
-    const int gc0 = c0 + 16 * tj0 + l16, gc1 = c0 + 16 * tj1 + l16;
+    if (gc < ncols) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int g = rl.grow[r];
-        if (g >= 0) {
-            GLB double* row = M + (int64_t)g * ldm;
-            if (gc0 < ncols) st_through(&row[gc0], acc0[r]);
-            if (two && gc1 < ncols) st_through(&row[gc1], acc1[r]);
+        for (int r = 0; r < 4; ++r) {
+            const int g0 = rl.grow[0][r], g1 = rl.grow[1][r];
+            if (g0 >= 0) st_through(&M[(int64_t)g0 * ldm + gc], acc0[r]);
+            if (g1 >= 0) st_through(&M[(int64_t)g1 * ldm + gc], acc1[r]);
         }
     }
 }
 
-// Every chunk of the sequence, in place; the first chunk is already in pre,
-// each next chunk is prefetched while the current one is multiplied.
-__device__ void apply_rotation(const ChunkSeq& cs, double (&pre)[JPF], uint32_t ok, const int* rowmap,
-                               double (*Ps)[JR + 1], double (*Xs)[JCH + 1])
+// Streaming: chunk 0 of the sequence is already in pre; each next chunk is
+// loaded into the other register set while the current one is multiplied.
+__device__ void apply_rotation(const ChunkSeq& cs, double (&pre)[JPF], uint32_t ok, const RotLane& rl,
+                               const int* rowmap)
 {
-    RotLane rl;
-    for (int ci = 0; ci < cs.nct; ++ci) {
-        store_chunk(pre, ok, Xs);
-        __syncthreads();
-        if (ci == 0) rot_lane_init(rl, Ps, rowmap);
-        if (ci + 1 < cs.nct) ok = cs.load(pre, ci + 1, rowmap);
+    double nxt[JPF];
+    for (int ci = 0; ci < cs.nct; ci += 2) {
+        uint32_t okn = 0;
+        if (ci + 1 < cs.nct) okn = cs.load(nxt, ci + 1, rowmap);
         GLB double* M;
         int64_t ldm;
         int ncols, c0;
         cs.select(ci, M, ldm, ncols, c0);
-        rotate_chunk(rl, Xs, M, ldm, ncols, c0);
-        __syncthreads();
+        rotate_chunk(rl, pre, ok, M, ldm, ncols, c0);
+        if (ci + 1 >= cs.nct) break;
+        if (ci + 2 < cs.nct) ok = cs.load(pre, ci + 2, rowmap);
+        cs.select(ci + 1, M, ldm, ncols, c0);
+        rotate_chunk(rl, nxt, okn, M, ldm, ncols, c0);
     }
 }
 
 constexpr int JAC_INNER_SWEEPS = 1;
 
-// Chunks already held in registers (res[ch] = chunk ch0 + ch of the
-// sequence): no global load on the way, only the LDS transpose for MFMA.
+// Resident: res[ch] is chunk ch0 + ch of the sequence; no load on the way.
 template <int NS>
-__device__ void apply_rotation_resident(const ChunkSeq& cs, double (&res)[NS][JPF], const uint32_t (&ok)[NS], int ch0,
-                                        int ch_end, const int* rowmap, double (*Ps)[JR + 1], double (*Xs)[JCH + 1])
+__device__ void apply_rotation_resident(const ChunkSeq& cs, const double (&res)[NS][JPF], const uint32_t (&ok)[NS],
+                                        int ch0, int ch_end, const RotLane& rl)
 {
-    RotLane rl;
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
         const int ci = ch0 + sl;
-        if (ci >= ch_end) break;  // uniform; no load below
-        store_chunk(res[sl], ok[sl], Xs);
-        __syncthreads();
-        if (sl == 0) rot_lane_init(rl, Ps, rowmap);
+        if (ci >= ch_end) break;  // uniform
         GLB double* M;
         int64_t ldm;
         int ncols, c0;
         cs.select(ci, M, ldm, ncols, c0);
-        rotate_chunk(rl, Xs, M, ldm, ncols, c0);
-        __syncthreads();
+        rotate_chunk(rl, res[sl], ok[sl], M, ldm, ncols, c0);
     }
 }
 
@@ -496,11 +487,14 @@ __device__ __forceinline__ int jacobi_pair_task(const JacDesc& d, int slot, int 
         update_p(p_i, q_i, rot_tab[(gsteps - 1) & 1][pr_i][0], rot_tab[(gsteps - 1) & 1][pr_i][1]);
 
     // ---- apply the accumulated rotation to the rows of X and of P
+    __syncthreads();  // Ps complete
+    RotLane rl;
+    rot_lane_init(rl, Ps, rowmap);
     if constexpr (RX > 0) {
-        apply_rotation_resident<RX>(seq, resx, okx, 0, seq.ncx, rowmap, Ps, Xs);
-        apply_rotation_resident<RP>(seq, resp, okp, seq.ncx, seq.nct, rowmap, Ps, Xs);
+        apply_rotation_resident<RX>(seq, resx, okx, 0, seq.ncx, rl);
+        apply_rotation_resident<RP>(seq, resp, okp, seq.ncx, seq.nct, rl);
     } else {
-        apply_rotation(seq, pre, okpre, rowmap, Ps, Xs);
+        apply_rotation(seq, pre, okpre, rl, rowmap);
     }
     return JAC_RAN;
 }
