@@ -55,9 +55,11 @@ constexpr int JAC_MAX_SWEEPS_FULL = 30;
 // Measured per batch: 64 x 1024^2 FP32 at l = 144 (n = 7.1 l) 8.4 -> 7.7 ms;
 // 32 x 500^2 at l = 110 (n = 4.5 l) 3.1 -> 2.9 ms; 32 x 512^2 at l = 272
 // (n = 1.9 l) 8.33 -> 8.35 ms, even (the Jacobi saves what the extra QR
-// costs); the 512-problem uneven batch with the cut at 1.5 l instead of 4 l
-// 308 -> 270 ms.  Plans without a saved forward only (the adjoint is that of
-// the plain path).
+// costs), and even again with the faster Jacobi rounds (6.80 -> 6.85 ms:
+// Jacobi 5.18 -> 4.59 ms, the QR of B^T and the products +0.63 ms); the
+// 512-problem uneven batch with the cut at 1.5 l instead of 4 l 308 -> 270
+// ms.  Plans without a saved forward only (the adjoint is that of the plain
+// path).
 constexpr double JAC_LQ_MIN_RATIO = 2.0;
 // From this many row blocks on, rounds 2.. of every sweep rotate only the
 // row pairs across the two blocks of a pair (half the inner steps): every
