@@ -170,9 +170,13 @@ def test_zero_and_nonfinite(lib):
 # ---------------------------------------------------------------- full SVD
 # 300^2, 512 x 280 and 280 x 512 have 19 and 18 row blocks of 16: from 16 blocks
 # on the Jacobi rounds 2.. of a sweep rotate only the cross-block row pairs,
-# the schedule the benchmark's 500^2 and 512^2 full SVDs run
+# the schedule the benchmark's 500^2 and 512^2 full SVDs run.  300 x 600 (and
+# its transpose) has Jacobi rows of 600 columns and 300 rows of P, more than
+# the register-resident variants hold, so its pairs stream their column
+# chunks; 200 x 900 takes the variant with eight column chunks resident.
 @pytest.mark.parametrize("m,n,k", [(64, 64, 20), (100, 37, 30), (37, 100, 30), (150, 150, 150), (5, 3, 2),
-                                   (300, 300, 120), (512, 280, 280), (280, 512, 200)])
+                                   (300, 300, 120), (512, 280, 280), (280, 512, 200), (300, 600, 150),
+                                   (600, 300, 150), (200, 900, 100)])
 def test_fullsvd_matches_oracle(lib, m, n, k):
     s = wl.spectrum_power(min(m, n), 1.0)
     A = wl.make_matrix(m, n, s, seed=51)
@@ -228,8 +232,13 @@ def test_persistent_jacobi_equals_round_launches(lib):
     in the same order per problem), for the RSVD, the triangular-factor path,
     FP32 storage and the full SVD."""
     shapes = [(100, 80, 20, 8, 2), (40, 200, 12, 6, 1), (130, 257, 33, 8, 2), (64, 64, 64, 0, 1), (33, 17, 5, 3, 0),
-              (90, 700, 24, 8, 2)]  # the last one takes the triangular-factor path (n >= 4 l)
-    mats = [wl.make_matrix(m, n, wl.spectrum_exp(min(m, n), 0.04 + 0.02 * i), seed=90 + i)
+              (90, 700, 24, 8, 2),  # the triangular-factor path (n >= 2 l)
+              (300, 600, 150, 8, 1)]  # full SVD: 600-column rows and 300 rows of P, the streaming Jacobi variant
+    # exp(-a i) spectra; the last one gentle (sigma_300 / sigma_1 = 2.5e-3): with
+    # singular values far below the FP64 floor the full SVD's one-sided Jacobi
+    # needs more sweeps than the plan's cap (the oracle takes 42 at a = 0.16)
+    decay = [0.04 + 0.02 * i for i in range(6)] + [0.02]
+    mats = [wl.make_matrix(m, n, wl.spectrum_exp(min(m, n), decay[i]), seed=90 + i)
             for i, (m, n, _, _, _) in enumerate(shapes)]
     probs = [dict(m=m, n=n, k=k, p=p, q=q, seed=95 + i) for i, (m, n, k, p, q) in enumerate(shapes)]
     for dtype, full in ((torch.float64, False), (torch.float32, False), (torch.float64, True)):
